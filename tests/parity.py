@@ -1,0 +1,145 @@
+"""Keypoint/descriptor comparison between an extraction result and the oracle.
+
+Decision rule: an oracle candidate is *decisive* when every margin it logged
+(pre-gate, extremum, Newton-step rounding, contrast, edge, orientation window
+radius, orientation peaks) exceeds ``MARGIN``; otherwise it is *marginal*
+and either outcome is accepted.  For decisive candidates the result under
+test must reproduce the oracle's accept/reject decision, the integer
+(octave, layer, row, col), the number of orientations, and the values within
+the tolerances below.  Every keypoint under test must come from an oracle
+candidate, or from a pixel whose candidate test is itself marginal.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+MARGIN = 1e-4
+TOL_XY = 1e-3          # input-image pixels
+TOL_ANGLE = 0.1        # degrees, circular
+TOL_DESC = 2e-3        # max-abs on the normalised descriptor
+TOL_REL = 1e-4         # sigma and response, relative
+
+MARGIN_KEYS = ("m_pre", "m_ext", "m_move", "m_con", "m_edge", "m_peak", "m_rad")
+
+
+def is_decisive(entry: dict, margin: float = MARGIN) -> bool:
+    return all(entry.get(k, math.inf) > margin for k in MARGIN_KEYS)
+
+
+def angle_diff(a, b):
+    d = np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)) % 360.0
+    return np.minimum(d, 360.0 - d)
+
+
+@dataclass
+class Report:
+    decisive_ok: int = 0
+    decisive_rejected: int = 0
+    marginal: int = 0
+    extra_marginal: int = 0
+    checked_keypoints: int = 0
+    max_err_xy: float = 0.0
+    max_err_angle: float = 0.0
+    max_err_desc: float = 0.0
+    max_err_rel: float = 0.0
+    mismatches: list = field(default_factory=list)
+
+    @property
+    def ok(self) -> bool:
+        return not self.mismatches
+
+    def summary(self) -> str:
+        return (f"decisive_ok={self.decisive_ok} decisive_rejected={self.decisive_rejected} "
+                f"marginal={self.marginal} extra_marginal={self.extra_marginal} "
+                f"checked_kp={self.checked_keypoints} max_xy={self.max_err_xy:.3g} "
+                f"max_angle={self.max_err_angle:.3g} max_desc={self.max_err_desc:.3g} "
+                f"max_rel={self.max_err_rel:.3g} mismatches={len(self.mismatches)}")
+
+
+def group_by_source(kps) -> dict:
+    """{(octave, src_layer, src_iy, src_ix): [row indices in order]}"""
+    groups: dict = {}
+    for k in range(len(kps)):
+        key = (int(kps["octave"][k]), int(kps["src_layer"][k]),
+               int(kps["src_iy"][k]), int(kps["src_ix"][k]))
+        groups.setdefault(key, []).append(k)
+    return groups
+
+
+def compare(oracle_result, kps, desc, params, oracle_mod, margin: float = MARGIN,
+            sample: set | None = None) -> Report:
+    """Compare keypoints ``kps`` (structured array with the oracle's field
+    names) and descriptors ``desc`` with ``oracle_result``.
+
+    ``sample``: optional set of candidate keys to restrict the check to (for
+    large inputs where the oracle describes only some candidates).
+    The check assumes no keypoint cap was hit on either side."""
+    rep = Report()
+    got = group_by_source(kps)
+    by_key = {(e["o"], e["i0"], e["r0"], e["c0"]): e for e in oracle_result.log}
+    octs = {oc.o: oc for oc in oracle_result.octaves}
+    for key, e in by_key.items():
+        if sample is not None and key not in sample:
+            continue
+        if not is_decisive(e, margin):
+            rep.marginal += 1
+            continue
+        rows = got.get(key, [])
+        if e["status"] != "ok":
+            rep.decisive_rejected += 1
+            if rows:
+                rep.mismatches.append((key, f"oracle rejected ({e['status']}) but result has "
+                                            f"{len(rows)} keypoints"))
+            continue
+        rep.decisive_ok += 1
+        angles = e["angles"]
+        if len(rows) != len(angles):
+            rep.mismatches.append((key, f"orientation count {len(rows)} != oracle {len(angles)}"))
+            continue
+        for k, row in enumerate(rows):
+            kp = kps[row]
+            if (int(kp["layer"]), int(kp["iy"]), int(kp["ix"])) != (e["i"], e["r"], e["c"]):
+                rep.mismatches.append((key, f"integer position {(int(kp['layer']), int(kp['iy']), int(kp['ix']))}"
+                                            f" != oracle {(e['i'], e['r'], e['c'])}"))
+                continue
+            exy = max(abs(float(kp["x"]) - e["x"]), abs(float(kp["y"]) - e["y"]))
+            ea = float(angle_diff(kp["angle"], angles[k]))
+            ed = float(np.max(np.abs(np.asarray(desc[row], dtype=np.float64) - e["desc"][k])))
+            er = max(abs(float(kp["sigma"]) - e["sigma"]) / e["sigma"],
+                     abs(float(kp["response"]) - e["response"]) / e["response"])
+            rep.max_err_xy = max(rep.max_err_xy, exy)
+            rep.max_err_angle = max(rep.max_err_angle, ea)
+            rep.max_err_desc = max(rep.max_err_desc, ed)
+            rep.max_err_rel = max(rep.max_err_rel, er)
+            rep.checked_keypoints += 1
+            bad = []
+            if exy > TOL_XY:
+                bad.append(f"xy err {exy:.3g}")
+            if ea > TOL_ANGLE:
+                bad.append(f"angle err {ea:.3g}")
+            if ed > TOL_DESC:
+                bad.append(f"desc err {ed:.3g}")
+            if er > TOL_REL:
+                bad.append(f"sigma/response rel err {er:.3g}")
+            if bad:
+                rep.mismatches.append((key, ", ".join(bad)))
+    # keypoints from pixels the oracle did not take as candidates
+    for key, rows in got.items():
+        if key in by_key:
+            continue
+        if sample is not None and key not in sample:
+            continue
+        o, i, r, c = key
+        oc = octs.get(o)
+        if oc is None:
+            rep.mismatches.append((key, "keypoint from an octave the oracle does not have"))
+            continue
+        m = oracle_mod.pixel_margins(oc.D, i, r, c, params)
+        if min(m["m_pre"], m["m_ext"]) <= margin:
+            rep.extra_marginal += 1
+        else:
+            rep.mismatches.append((key, f"not an oracle candidate (margins {m})"))
+    return rep
