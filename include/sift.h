@@ -1,0 +1,196 @@
+/*
+ * sift.h -- C ABI of the GPU-resident SIFT extraction library (gfx950).
+ *
+ * The library computes, for float32 grayscale images already resident in
+ * device memory, the SIFT pipeline the paper lays out in Eq. (1) and its
+ * method section (3.2): Gaussian scale space with 4-sigma truncated separable
+ * kernels, DoG, 26-neighbour extrema with a contrast pre-gate, sub-pixel
+ * refinement by a 3-D Taylor expansion solved with Cramer's rule (at most 5
+ * steps) plus Hessian edge rejection, a 36-bin orientation histogram with
+ * [1/4, 1/2, 1/4] smoothing and parabolic peak refinement, and the 4x4x8
+ * gradient-histogram descriptor with optional domain-size pooling (DSP, the
+ * "DSP Multi-Scale Descriptor Pooling" paragraph) and RootSIFT (the "RootSIFT
+ * Normalization" paragraph).  Everything on the path is deterministic: the
+ * same inputs give bit-identical outputs run after run, and an image gives
+ * the same bits alone or inside any batch.
+ *
+ * Conventions
+ *  - Every call returns sift_status; nothing throws across the ABI.
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are ordinary host memory read during the call only.
+ *  - Extraction calls only enqueue work on `stream` (a hipStream_t passed as
+ *    void*; NULL = the default stream) and return; outputs are valid once the
+ *    stream has reached that point.  They never allocate device memory, copy
+ *    to or from the host, or synchronise, so they may be captured in a HIP
+ *    graph.
+ *  - Argument errors are reported synchronously before anything is enqueued.
+ *  - A handle is immutable after sift_create and may be shared by threads.
+ *    A workspace must not be used by two extractions in flight at once.
+ *  - Image pixel (r, c) sits at x = c, y = r; y grows downwards.  Angles are
+ *    degrees in [0, 360), measured from +x towards +y.
+ */
+#ifndef SIFT_MI355X_H
+#define SIFT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SIFT_OK = 0,
+  SIFT_ERR_INVALID_ARG = 1,         /* null pointer, bad parameter, h/w <= 0, pitch < w */
+  SIFT_ERR_IMAGE_TOO_SMALL = 2,     /* last octave would have min(h, w) < 2*border + 3 */
+  SIFT_ERR_WORKSPACE_TOO_SMALL = 3, /* workspace_bytes below what *_workspace_size gives */
+  SIFT_ERR_TOO_LARGE = 4,           /* image or batch beyond the library's index limits */
+  SIFT_ERR_HIP = 5,                 /* HIP runtime error; sift_last_error() has the text */
+  SIFT_ERR_NOT_SUPPORTED = 6        /* a parameter value the kernels do not implement */
+} sift_status;
+
+#define SIFT_MAX_DSP 16
+#define SIFT_DESC_DIM 128
+
+/* Extraction settings.  sift_params_default() fills the values noted. */
+typedef struct {
+  int32_t n_octaves;          /* 4: octaves 0..n_octaves-1 (plus -1 when upsample) */
+  int32_t n_scales;           /* 3: s, DoG layers searched per octave, 1..6 */
+  int32_t upsample;           /* 0: 1 adds octave -1 from a 2x bilinear upsample */
+  float sigma0;               /* 1.6: blur of level 0 of each octave, octave pixels */
+  float sigma_in;             /* 0.5: blur assumed present in the input */
+  float contrast_threshold;   /* 0.04/3: |D(x^)| threshold, image values in [0,1] */
+  float prefilter_ratio;      /* 0.5: candidate pre-gate |D| > ratio * threshold */
+  float edge_ratio;           /* 10: Hessian principal-curvature ratio bound */
+  int32_t border;             /* 5: frame of each octave not searched, >= 1 */
+  int32_t refine_iters;       /* 5: Newton steps before a candidate is dropped */
+  int32_t ori_bins;           /* 36: orientation histogram bins (fixed) */
+  float ori_sigma_factor;     /* 1.5: orientation window sigma / keypoint sigma */
+  float ori_radius_factor;    /* 3.0: window radius = round(factor * window sigma) */
+  float ori_peak_ratio;       /* 0.8: secondary peaks kept down to ratio * max */
+  int32_t upright;            /* 0: 1 assigns the single angle 0 */
+  int32_t desc_width;         /* 4: spatial cells per side (fixed) */
+  int32_t desc_ori_bins;      /* 8: orientation bins per cell (fixed) */
+  float desc_magnif;          /* 3.0: cell width / keypoint sigma */
+  float desc_clamp;           /* 0.2: clamp after the first L2 normalisation */
+  int32_t n_dsp;              /* 1: number of domain sizes pooled (1..SIFT_MAX_DSP) */
+  float dsp_scales[SIFT_MAX_DSP]; /* {1}: domain sizes relative to the keypoint scale */
+  int32_t rootsift;           /* 0: 1 applies L1 normalisation then sqrt */
+  int32_t max_keypoints;      /* 65536: keypoints kept per image (canonical order) */
+  int32_t max_candidates;     /* 65536: detections refined per image (canonical order) */
+} sift_params;
+
+/* One keypoint, 48 bytes.  Keypoints of an image come in canonical order:
+ * by the detection they were refined from -- (octave, src_layer, src_iy,
+ * src_ix) ascending -- then by ascending orientation bin. */
+typedef struct {
+  float x, y;          /* input-image pixel coordinates of the refined extremum */
+  float sigma;         /* scale in input-image pixels */
+  float angle;         /* degrees, [0, 360) */
+  float response;      /* |D(x^)|, the interpolated DoG magnitude */
+  int32_t octave;      /* -1 .. n_octaves-1 */
+  int32_t layer;       /* DoG layer 1..n_scales after refinement */
+  int32_t ix, iy;      /* integer pixel after refinement, octave coordinates */
+  int32_t src_layer;   /* the detection this keypoint was refined from: */
+  int32_t src_iy;      /*   layer, row and column in octave coordinates */
+  int32_t src_ix;
+} sift_keypoint;
+
+/* Where one image's results go; every pointer is device memory owned by the
+ * caller.  keypoints[capacity], descriptors[capacity][128] row-major
+ * (index (row_cell*4 + col_cell)*8 + orientation_bin).  On completion:
+ * *count = min(*n_found, capacity, max_keypoints); *n_found = keypoints
+ * produced from the refined detections; *n_candidates = detections found
+ * (may exceed max_candidates, in which case only the first max_candidates in
+ * canonical order were refined).  Any of n_found / n_candidates may be NULL. */
+typedef struct {
+  sift_keypoint* keypoints;
+  float* descriptors;
+  int32_t* count;
+  int32_t* n_found;
+  int32_t* n_candidates;
+  int32_t capacity;
+} sift_output;
+
+typedef struct sift_handle sift_handle;
+
+/* Fill *p with the defaults listed above.  Errors: INVALID_ARG if p is NULL. */
+sift_status sift_params_default(sift_params* p);
+
+/* Validate *p and create an immutable handle (host memory only; no device
+ * allocation).  Errors: INVALID_ARG / NOT_SUPPORTED for bad or unimplemented
+ * settings.  The caller releases the handle with sift_destroy. */
+sift_status sift_create(const sift_params* p, sift_handle** out);
+void sift_destroy(sift_handle* h);
+
+/* Copy the handle's settings into *p. */
+sift_status sift_get_params(const sift_handle* h, sift_params* p);
+
+/* Device workspace bytes sift_extract needs for a height x width image.
+ * Errors: INVALID_ARG, IMAGE_TOO_SMALL, TOO_LARGE. */
+sift_status sift_workspace_size(const sift_handle* h, int32_t height, int32_t width,
+                                size_t* bytes);
+
+/* Extract one image: d_image is a device float32 array of height rows of
+ * `pitch` elements (pitch >= width), values nominally in [0, 1].
+ * d_workspace (device, >= sift_workspace_size bytes, 256-byte aligned) holds
+ * the pyramid and all intermediate state; its contents on entry do not
+ * matter.  Results land in *out (see sift_output). */
+sift_status sift_extract(sift_handle* h, const float* d_image, int32_t height, int32_t width,
+                         int64_t pitch, void* d_workspace, size_t workspace_bytes,
+                         const sift_output* out, void* stream);
+
+/* Workspace bytes for a batch of n images with the given sizes (host arrays). */
+sift_status sift_batch_workspace_size(const sift_handle* h, int32_t n, const int32_t* heights,
+                                      const int32_t* widths, size_t* bytes);
+
+/* Extract n images of possibly different sizes in one launch sequence:
+ * every stage runs once for the whole batch over (image, octave, tile) work
+ * items.  d_images, heights, widths, pitches and outs are host arrays of n
+ * entries (d_images[k] is a device pointer).  Each image's results are
+ * bit-identical to sift_extract on that image alone. */
+sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_images,
+                               const int32_t* heights, const int32_t* widths,
+                               const int64_t* pitches, void* d_workspace,
+                               size_t workspace_bytes, const sift_output* outs, void* stream);
+
+/* Inspection of a workspace after sift_extract (tests and tooling): device
+ * address of Gaussian level `level` (0..n_scales+2) of octave `octave`
+ * (-1 or 0 .. n_octaves-1) for an image of height x width placed at
+ * d_workspace, with its size and row pitch in elements.  Levels are stored
+ * relative to mid-grey: the value held is L - 0.5. */
+sift_status sift_workspace_level(const sift_handle* h, int32_t height, int32_t width,
+                                 const void* d_workspace, int32_t octave, int32_t level,
+                                 const float** d_level, int32_t* level_height,
+                                 int32_t* level_width, int32_t* level_pitch);
+
+/* Stage profiling (benchmarks and tests; not for production paths).
+ * sift_profile_start begins recording, for every extraction this process then
+ * enqueues, a HIP event before and after each stage on the extraction's
+ * stream, together with the stage's algorithmic HBM bytes (what the stage must
+ * read and write at least: each pyramid level read once and written once,
+ * detection reading the s+3 levels once, ...).  sift_profile_stop waits for
+ * the recorded events, writes per-stage totals into stats[0..max_stats-1],
+ * sets *n_stats and ends recording.  Recording is process-wide; call
+ * start/stop from one thread.  Errors: HIP if event creation or timing fails,
+ * INVALID_ARG for null arguments or stop without start. */
+typedef struct {
+  char name[32];        /* stage: "blur", "detect", "describe", ... */
+  int32_t launches;     /* kernel launches recorded */
+  double ms;            /* summed event time over the launches */
+  double bytes;         /* summed algorithmic bytes over the launches */
+} sift_stage_stat;
+
+sift_status sift_profile_start(void);
+sift_status sift_profile_stop(sift_stage_stat* stats, int32_t max_stats, int32_t* n_stats);
+
+/* Static text for a status code. */
+const char* sift_status_string(sift_status st);
+/* Detail of the last error on the calling thread ("" if none). */
+const char* sift_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIFT_MI355X_H */

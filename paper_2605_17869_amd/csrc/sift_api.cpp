@@ -1,0 +1,501 @@
+// Host runtime of the SIFT library: parameter validation, Gaussian taps,
+// workspace layout, and the launch sequence of one extraction.  Nothing here
+// allocates device memory or synchronises; every extraction is a fixed
+// sequence of kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sift.h"
+#include "sift_internal.h"
+#include "sift_launch.h"
+
+using namespace sift;
+
+namespace {
+
+thread_local std::string g_error;
+
+sift_status fail(sift_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return st;
+}
+
+constexpr int kMaxSide = 32768;    // per input dimension
+constexpr int kMaxBatch = 4096;
+constexpr int kBlurTileH = 32;
+
+// Sampled Gaussian exp(-t^2 / (2 sigma^2)), t = -R..R, R = ceil(4 sigma),
+// normalised by its double-precision sum and rounded to float.
+struct Taps {
+  int radius = 0;
+  float g[2 * kMaxRadius + 1] = {};
+};
+
+bool make_taps(double sigma, Taps* t) {
+  const int r = (int)std::ceil(4.0 * sigma);
+  if (r < 1 || r > kMaxRadius) return false;
+  double w[2 * kMaxRadius + 1];
+  double sum = 0.0;
+  for (int i = -r; i <= r; ++i) {
+    w[i + r] = std::exp(-(double)(i * i) / (2.0 * sigma * sigma));
+    sum += w[i + r];
+  }
+  t->radius = r;
+  for (int i = 0; i < 2 * r + 1; ++i) t->g[i] = (float)(w[i] / sum);
+  return true;
+}
+
+}  // namespace
+
+struct sift_handle {
+  sift_params params;
+  DevParams dev;
+  Taps init;                       // first level of the first octave
+  Taps inc[kMaxScales + 2];        // level i from level i-1, i = 1..s+2
+};
+
+namespace {
+
+sift_status validate_params(const sift_params& p) {
+  if (p.n_octaves < 1) return fail(SIFT_ERR_INVALID_ARG, "n_octaves must be >= 1");
+  if (p.upsample != 0 && p.upsample != 1) return fail(SIFT_ERR_INVALID_ARG, "upsample must be 0 or 1");
+  if (p.n_octaves + p.upsample > kMaxOct)
+    return fail(SIFT_ERR_NOT_SUPPORTED, "at most %d octaves", kMaxOct);
+  if (p.n_scales < 1 || p.n_scales > kMaxScales)
+    return fail(SIFT_ERR_NOT_SUPPORTED, "n_scales must be in 1..%d", kMaxScales);
+  if (!(p.sigma0 > 0.0f) || !(p.sigma_in >= 0.0f))
+    return fail(SIFT_ERR_INVALID_ARG, "sigma0 must be > 0 and sigma_in >= 0");
+  if (!(p.contrast_threshold > 0.0f) || !(p.prefilter_ratio >= 0.0f) || !(p.edge_ratio > 0.0f))
+    return fail(SIFT_ERR_INVALID_ARG, "thresholds must be positive");
+  if (p.border < 1) return fail(SIFT_ERR_INVALID_ARG, "border must be >= 1");
+  if (p.refine_iters < 1 || p.refine_iters > 64)
+    return fail(SIFT_ERR_INVALID_ARG, "refine_iters must be in 1..64");
+  if (p.ori_bins != kOriBins) return fail(SIFT_ERR_NOT_SUPPORTED, "ori_bins must be 36");
+  if (!(p.ori_sigma_factor > 0.0f) || !(p.ori_radius_factor > 0.0f) ||
+      !(p.ori_peak_ratio > 0.0f && p.ori_peak_ratio <= 1.0f))
+    return fail(SIFT_ERR_INVALID_ARG, "bad orientation settings");
+  if (p.upright != 0 && p.upright != 1) return fail(SIFT_ERR_INVALID_ARG, "upright must be 0 or 1");
+  if (p.desc_width != 4 || p.desc_ori_bins != 8)
+    return fail(SIFT_ERR_NOT_SUPPORTED, "descriptor must be 4x4x8");
+  if (!(p.desc_magnif > 0.0f) || !(p.desc_clamp > 0.0f))
+    return fail(SIFT_ERR_INVALID_ARG, "bad descriptor settings");
+  if (p.n_dsp < 1 || p.n_dsp > SIFT_MAX_DSP)
+    return fail(SIFT_ERR_INVALID_ARG, "n_dsp must be in 1..%d", SIFT_MAX_DSP);
+  for (int i = 0; i < p.n_dsp; ++i)
+    if (!(p.dsp_scales[i] > 0.0f) || !(p.dsp_scales[i] < 64.0f))
+      return fail(SIFT_ERR_INVALID_ARG, "dsp_scales[%d] must be in (0, 64)", i);
+  if (p.rootsift != 0 && p.rootsift != 1) return fail(SIFT_ERR_INVALID_ARG, "rootsift must be 0 or 1");
+  if (p.max_keypoints < 0) return fail(SIFT_ERR_INVALID_ARG, "max_keypoints must be >= 0");
+  if (p.max_candidates < 1 || p.max_candidates > (1 << 24))
+    return fail(SIFT_ERR_INVALID_ARG, "max_candidates must be in 1..2^24");
+  return SIFT_OK;
+}
+
+// Octave count, size limits and the last-octave minimum.
+sift_status validate_size(const sift_handle* h, int height, int width) {
+  if (height < 1 || width < 1) return fail(SIFT_ERR_INVALID_ARG, "image size must be positive");
+  if (height > kMaxSide || width > kMaxSide)
+    return fail(SIFT_ERR_TOO_LARGE, "image side above %d", kMaxSide);
+  int hk, wk;
+  octave_dims(height, width, h->dev.upsample, h->dev.n_oct - 1, &hk, &wk);
+  const int need = 2 * h->dev.border + 3;
+  if (hk < need || wk < need)
+    return fail(SIFT_ERR_IMAGE_TOO_SMALL, "last octave %dx%d below %dx%d", hk, wk, need, need);
+  return SIFT_OK;
+}
+
+int64_t region_bytes(const sift_handle* h, int height, int width) {
+  return region_tail(height, width, layout_cfg(h->dev)).bytes;
+}
+
+sift_status check_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return SIFT_OK;
+  return fail(SIFT_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- stage profiling: event pairs around stages while recording is on
+enum Stage { kStSetup, kStBlur, kStDetect, kStCompact, kStRefine, kStOrient, kStDescribe, kStCount };
+const char* const kStageNames[kStCount] = {"setup", "blur", "detect", "compact",
+                                           "refine", "orient", "describe"};
+
+struct ProfRecord {
+  int stage;
+  double bytes;
+  hipEvent_t a, b;
+};
+
+struct Profiler {
+  bool on = false;
+  std::vector<ProfRecord> recs;
+  std::vector<hipEvent_t> pool;
+} g_prof;
+
+hipEvent_t prof_event() {
+  if (!g_prof.pool.empty()) {
+    hipEvent_t e = g_prof.pool.back();
+    g_prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Opens a stage record (no-op when recording is off); close with prof_end.
+int prof_begin(int stage, double bytes, hipStream_t stream) {
+  if (!g_prof.on) return -1;
+  ProfRecord r;
+  r.stage = stage;
+  r.bytes = bytes;
+  r.a = prof_event();
+  r.b = prof_event();
+  if (!r.a || !r.b) return -1;
+  hipEventRecord(r.a, stream);
+  g_prof.recs.push_back(r);
+  return (int)g_prof.recs.size() - 1;
+}
+
+void prof_end(int rec, hipStream_t stream) {
+  if (rec < 0) return;
+  hipEventRecord(g_prof.recs[rec].b, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+sift_status sift_params_default(sift_params* p) {
+  if (!p) return fail(SIFT_ERR_INVALID_ARG, "null params");
+  std::memset(p, 0, sizeof *p);
+  p->n_octaves = 4;
+  p->n_scales = 3;
+  p->upsample = 0;
+  p->sigma0 = 1.6f;
+  p->sigma_in = 0.5f;
+  p->contrast_threshold = 0.04f / 3.0f;
+  p->prefilter_ratio = 0.5f;
+  p->edge_ratio = 10.0f;
+  p->border = 5;
+  p->refine_iters = 5;
+  p->ori_bins = 36;
+  p->ori_sigma_factor = 1.5f;
+  p->ori_radius_factor = 3.0f;
+  p->ori_peak_ratio = 0.8f;
+  p->upright = 0;
+  p->desc_width = 4;
+  p->desc_ori_bins = 8;
+  p->desc_magnif = 3.0f;
+  p->desc_clamp = 0.2f;
+  p->n_dsp = 1;
+  p->dsp_scales[0] = 1.0f;
+  p->rootsift = 0;
+  p->max_keypoints = 65536;
+  p->max_candidates = 65536;
+  return SIFT_OK;
+}
+
+sift_status sift_create(const sift_params* p, sift_handle** out) {
+  if (!p || !out) return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  sift_status st = validate_params(*p);
+  if (st != SIFT_OK) return st;
+  sift_handle* h = new sift_handle();
+  h->params = *p;
+  DevParams& d = h->dev;
+  std::memset(&d, 0, sizeof d);
+  d.n_oct = p->n_octaves + p->upsample;
+  d.o0 = p->upsample ? -1 : 0;
+  d.s = p->n_scales;
+  d.upsample = p->upsample;
+  d.border = p->border;
+  d.refine_iters = p->refine_iters;
+  d.upright = p->upright;
+  d.rootsift = p->rootsift;
+  d.max_kp = p->max_keypoints;
+  d.max_cand = p->max_candidates;
+  d.n_dsp = p->n_dsp;
+  d.blur_th = kBlurTileH;
+  d.sigma0 = p->sigma0;
+  d.contrast_thr = p->contrast_threshold;
+  d.pre_thr = p->prefilter_ratio * p->contrast_threshold;
+  d.edge_ratio = p->edge_ratio;
+  d.ori_sigma_factor = p->ori_sigma_factor;
+  d.ori_radius_factor = p->ori_radius_factor;
+  d.ori_peak_ratio = p->ori_peak_ratio;
+  d.desc_magnif = p->desc_magnif;
+  d.desc_clamp = p->desc_clamp;
+  for (int i = 0; i < p->n_dsp; ++i) d.dsp[i] = p->dsp_scales[i];
+  // level sigmas: level i of an octave carries sigma0 * k^i, k = 2^(1/s)
+  const double s0 = p->sigma0;
+  const double assumed = (double)p->sigma_in * (p->upsample ? 2.0 : 1.0);
+  const double sig_init = std::sqrt(std::fmax(s0 * s0 - assumed * assumed, 0.01));
+  const double k2 = std::pow(2.0, 2.0 / p->n_scales);
+  bool ok = make_taps(sig_init, &h->init);
+  for (int i = 1; i <= p->n_scales + 2; ++i)
+    ok = ok && make_taps(s0 * std::sqrt(std::pow(k2, i) - std::pow(k2, i - 1)), &h->inc[i - 1]);
+  if (!ok) {
+    delete h;
+    return fail(SIFT_ERR_NOT_SUPPORTED, "a Gaussian radius ceil(4 sigma) exceeds %d", kMaxRadius);
+  }
+  *out = h;
+  return SIFT_OK;
+}
+
+void sift_destroy(sift_handle* h) { delete h; }
+
+sift_status sift_get_params(const sift_handle* h, sift_params* p) {
+  if (!h || !p) return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  *p = h->params;
+  return SIFT_OK;
+}
+
+sift_status sift_batch_workspace_size(const sift_handle* h, int32_t n, const int32_t* heights,
+                                      const int32_t* widths, size_t* bytes) {
+  if (!h || !heights || !widths || !bytes) return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  if (n < 1) return fail(SIFT_ERR_INVALID_ARG, "batch size must be >= 1");
+  if (n > kMaxBatch) return fail(SIFT_ERR_TOO_LARGE, "batch above %d images", kMaxBatch);
+  Header hd;
+  make_header(n, &hd);
+  int64_t total = hd.bytes;
+  for (int i = 0; i < n; ++i) {
+    sift_status st = validate_size(h, heights[i], widths[i]);
+    if (st != SIFT_OK) return st;
+    total += region_bytes(h, heights[i], widths[i]);
+  }
+  *bytes = (size_t)total;
+  return SIFT_OK;
+}
+
+sift_status sift_workspace_size(const sift_handle* h, int32_t height, int32_t width, size_t* bytes) {
+  return sift_batch_workspace_size(h, 1, &height, &width, bytes);
+}
+
+sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_images,
+                               const int32_t* heights, const int32_t* widths,
+                               const int64_t* pitches, void* d_workspace,
+                               size_t workspace_bytes, const sift_output* outs, void* stream_v) {
+  if (!h || !d_images || !heights || !widths || !pitches || !d_workspace || !outs)
+    return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  if (n < 1) return fail(SIFT_ERR_INVALID_ARG, "batch size must be >= 1");
+  if (n > kMaxBatch) return fail(SIFT_ERR_TOO_LARGE, "batch above %d images", kMaxBatch);
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+    return fail(SIFT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  for (int i = 0; i < n; ++i) {
+    if (!d_images[i]) return fail(SIFT_ERR_INVALID_ARG, "image %d is null", i);
+    if (pitches[i] < widths[i]) return fail(SIFT_ERR_INVALID_ARG, "image %d: pitch < width", i);
+    if (!outs[i].keypoints || !outs[i].descriptors || !outs[i].count)
+      return fail(SIFT_ERR_INVALID_ARG, "image %d: null output pointer", i);
+    if (outs[i].capacity < 0) return fail(SIFT_ERR_INVALID_ARG, "image %d: negative capacity", i);
+  }
+  size_t need = 0;
+  sift_status st = sift_batch_workspace_size(h, n, heights, widths, &need);
+  if (st != SIFT_OK) return st;
+  if (workspace_bytes < need)
+    return fail(SIFT_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
+
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+  char* ws = static_cast<char*>(d_workspace);
+  const DevParams& p = h->dev;
+  const LayoutCfg lc = layout_cfg(p);
+  Header hd;
+  make_header(n, &hd);
+  HdrPtrs hp;
+  hp.table = reinterpret_cast<const ImgEntry*>(ws + hd.table);
+  hp.tile_prefix = reinterpret_cast<int*>(ws + hd.tile_prefix);
+  hp.band_prefix = reinterpret_cast<int*>(ws + hd.band_prefix);
+  hp.cand_prefix = reinterpret_cast<int*>(ws + hd.cand_prefix);
+  hp.kp_prefix = reinterpret_cast<int*>(ws + hd.kp_prefix);
+
+  // image table, a chunk of entries per launch
+  int prec = prof_begin(kStSetup, 0.0, stream);
+  std::vector<int64_t> tiles(p.n_oct, 0);
+  std::vector<int64_t> pixels(p.n_oct, 0);
+  int64_t input_px = 0;
+  int64_t bands = 0;
+  int64_t off = hd.bytes;
+  SetupChunk chunk;
+  std::memset(&chunk, 0, sizeof chunk);
+  for (int i = 0; i < n; ++i) {
+    ImgEntry& e = chunk.e[chunk.count];
+    e.src = d_images[i];
+    e.src_pitch = pitches[i];
+    e.h = heights[i];
+    e.w = widths[i];
+    e.region = off;
+    e.kp = outs[i].keypoints;
+    e.desc = outs[i].descriptors;
+    e.count = outs[i].count;
+    e.n_found = outs[i].n_found;
+    e.n_cand = outs[i].n_candidates;
+    e.cap = outs[i].capacity;
+    e.pad = 0;
+    off += region_bytes(h, heights[i], widths[i]);
+    for (int k = 0; k < p.n_oct; ++k) {
+      int hk, wk;
+      octave_dims(heights[i], widths[i], p.upsample, k, &hk, &wk);
+      tiles[k] += cdiv(wk, kTileW) * cdiv(hk, p.blur_th);
+      pixels[k] += (int64_t)hk * wk;
+    }
+    input_px += (int64_t)heights[i] * widths[i];
+    bands += region_tail(heights[i], widths[i], lc).total_bands;
+    if (++chunk.count == kSetupChunk || i == n - 1) {
+      if ((st = check_hip(launch_setup(hp, chunk, stream), "setup")) != SIFT_OK) return st;
+      chunk.first = i + 1;
+      chunk.count = 0;
+    }
+  }
+  for (int k = 0; k < p.n_oct; ++k)
+    if (tiles[k] > INT32_MAX) return fail(SIFT_ERR_TOO_LARGE, "batch has too many tiles");
+  if (bands > INT32_MAX) return fail(SIFT_ERR_TOO_LARGE, "batch has too many bands");
+  if ((st = check_hip(launch_finalize(hp, n, p, stream), "finalize")) != SIFT_OK) return st;
+  prof_end(prec, stream);
+
+  // scale space: one launch per (octave, level) over every image of the batch
+  for (int k = 0; k < p.n_oct; ++k) {
+    for (int lv = (k == 0 ? 0 : 1); lv <= p.s + 2; ++lv) {
+      BlurArgs a;
+      std::memset(&a, 0, sizeof a);
+      a.ws = ws;
+      a.table = hp.table;
+      a.tile_prefix = hp.tile_prefix + (int64_t)k * (n + 1);
+      a.n = n;
+      a.k = k;
+      a.dst_level = lv;
+      a.th = p.blur_th;
+      a.p = p;
+      const Taps& t = lv == 0 ? h->init : h->inc[lv - 1];
+      if (lv == 0) a.mode = p.upsample ? kSrcUpsample : kSrcImage;
+      else if (lv == 1 && k > 0) a.mode = kSrcDown;
+      else a.mode = kSrcLevel;
+      std::memcpy(a.taps, t.g, sizeof(float) * (2 * t.radius + 1));
+      // algorithmic bytes: the source read once (input pixels for the first
+      // level), the level written once, plus level 0 written when subsampling
+      double bytes = 8.0 * pixels[k];
+      if (lv == 0 && p.upsample) bytes = 4.0 * pixels[k] + 4.0 * input_px;
+      if (a.mode == kSrcDown) bytes += 4.0 * pixels[k];
+      prec = prof_begin(kStBlur, bytes, stream);
+      if ((st = check_hip(launch_blur(a, t.radius, (int)tiles[k], stream), "blur")) != SIFT_OK) return st;
+      prof_end(prec, stream);
+    }
+  }
+  // detection and ordered compaction
+  int64_t all_px = 0;
+  for (int k = 0; k < p.n_oct; ++k) all_px += pixels[k];
+  // detection reads the s+3 levels once and writes one mask bit per pixel-layer
+  prec = prof_begin(kStDetect, (4.0 * (p.s + 3) + p.s / 8.0) * all_px, stream);
+  if ((st = check_hip(launch_detect(ws, hp, n, p, (int)bands, stream), "detect")) != SIFT_OK) return st;
+  prof_end(prec, stream);
+  prec = prof_begin(kStCompact, (p.s / 4.0) * all_px, stream);
+  if ((st = check_hip(launch_band_scan(ws, hp, n, p, stream), "band scan")) != SIFT_OK) return st;
+  if ((st = check_hip(launch_emit(ws, hp, n, p, (int)bands, stream), "emit")) != SIFT_OK) return st;
+  if ((st = check_hip(launch_img_prefix(ws, hp, n, p, 0, stream), "prefix")) != SIFT_OK) return st;
+  prof_end(prec, stream);
+  // per-candidate stages; grids are persistent, work counts are read on the device
+  const int64_t cand_total = (int64_t)n * p.max_cand;
+  const int refine_grid = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (cand_total + 255) / 256));
+  const int orient_grid = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (cand_total + 3) / 4));
+  prec = prof_begin(kStRefine, 0.0, stream);
+  if ((st = check_hip(launch_refine(ws, hp, n, p, refine_grid, stream), "refine")) != SIFT_OK) return st;
+  prof_end(prec, stream);
+  prec = prof_begin(kStOrient, 0.0, stream);
+  if ((st = check_hip(launch_orient(ws, hp, n, p, orient_grid, stream), "orient")) != SIFT_OK) return st;
+  if ((st = check_hip(launch_ori_scan(ws, hp, n, p, stream), "orientation scan")) != SIFT_OK) return st;
+  if ((st = check_hip(launch_img_prefix(ws, hp, n, p, 1, stream), "prefix")) != SIFT_OK) return st;
+  prof_end(prec, stream);
+  const int desc_grid = (int)std::min<int64_t>(4096, std::max<int64_t>(1, cand_total));
+  prec = prof_begin(kStDescribe, 0.0, stream);
+  if ((st = check_hip(launch_describe(ws, hp, n, p, desc_grid, stream), "describe")) != SIFT_OK) return st;
+  prof_end(prec, stream);
+  return SIFT_OK;
+}
+
+sift_status sift_extract(sift_handle* h, const float* d_image, int32_t height, int32_t width,
+                         int64_t pitch, void* d_workspace, size_t workspace_bytes,
+                         const sift_output* out, void* stream) {
+  return sift_extract_batch(h, 1, &d_image, &height, &width, &pitch, d_workspace, workspace_bytes,
+                            out, stream);
+}
+
+sift_status sift_workspace_level(const sift_handle* h, int32_t height, int32_t width,
+                                 const void* d_workspace, int32_t octave, int32_t level,
+                                 const float** d_level, int32_t* level_height,
+                                 int32_t* level_width, int32_t* level_pitch) {
+  if (!h || !d_workspace || !d_level || !level_height || !level_width || !level_pitch)
+    return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  sift_status st = validate_size(h, height, width);
+  if (st != SIFT_OK) return st;
+  const int k = octave - h->dev.o0;
+  if (k < 0 || k >= h->dev.n_oct) return fail(SIFT_ERR_INVALID_ARG, "no octave %d", octave);
+  if (level < 0 || level > h->dev.s + 2) return fail(SIFT_ERR_INVALID_ARG, "no level %d", level);
+  Header hd;
+  make_header(1, &hd);
+  const OctView ov = octave_view(height, width, layout_cfg(h->dev), k);
+  *d_level = reinterpret_cast<const float*>(static_cast<const char*>(d_workspace) + hd.bytes +
+                                            ov.level0 + (int64_t)level * ov.plane);
+  *level_height = ov.h;
+  *level_width = ov.w;
+  *level_pitch = ov.pitch;
+  return SIFT_OK;
+}
+
+sift_status sift_profile_start(void) {
+  g_prof.on = true;
+  return SIFT_OK;
+}
+
+sift_status sift_profile_stop(sift_stage_stat* stats, int32_t max_stats, int32_t* n_stats) {
+  if (!stats || !n_stats || max_stats < 0) return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  if (!g_prof.on) return fail(SIFT_ERR_INVALID_ARG, "profiling was not started");
+  g_prof.on = false;
+  sift_stage_stat tot[kStCount];
+  std::memset(tot, 0, sizeof tot);
+  for (int s = 0; s < kStCount; ++s) std::snprintf(tot[s].name, sizeof tot[s].name, "%s", kStageNames[s]);
+  sift_status st = SIFT_OK;
+  for (ProfRecord& r : g_prof.recs) {
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess && st == SIFT_OK) st = check_hip(e, "profile events");
+    tot[r.stage].launches += 1;
+    tot[r.stage].ms += ms;
+    tot[r.stage].bytes += r.bytes;
+    g_prof.pool.push_back(r.a);
+    g_prof.pool.push_back(r.b);
+  }
+  g_prof.recs.clear();
+  int k = 0;
+  for (int s = 0; s < kStCount && k < max_stats; ++s)
+    if (tot[s].launches) stats[k++] = tot[s];
+  *n_stats = k;
+  return st;
+}
+
+const char* sift_status_string(sift_status st) {
+  switch (st) {
+    case SIFT_OK: return "ok";
+    case SIFT_ERR_INVALID_ARG: return "invalid argument";
+    case SIFT_ERR_IMAGE_TOO_SMALL: return "image too small";
+    case SIFT_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case SIFT_ERR_TOO_LARGE: return "too large";
+    case SIFT_ERR_HIP: return "HIP error";
+    case SIFT_ERR_NOT_SUPPORTED: return "not supported";
+  }
+  return "unknown status";
+}
+
+const char* sift_last_error(void) { return g_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,39 @@
+// Launch helpers exported by the kernel translation unit to the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sift_internal.h"
+
+namespace sift {
+
+struct SetupChunk {
+  int first;
+  int count;
+  ImgEntry e[kSetupChunk];
+};
+
+// Each helper enqueues one kernel on `stream` and returns the launch status.
+hipError_t launch_setup(const HdrPtrs& hp, const SetupChunk& c, hipStream_t stream);
+hipError_t launch_finalize(const HdrPtrs& hp, int n, const DevParams& p, hipStream_t stream);
+// Gaussian level: `radius` selects the instantiation; taps in a.taps[0..2R].
+hipError_t launch_blur(const BlurArgs& a, int radius, int grid, hipStream_t stream);
+hipError_t launch_detect(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
+                         hipStream_t stream);
+hipError_t launch_band_scan(char* ws, const HdrPtrs& hp, int n, const DevParams& p,
+                         hipStream_t stream);
+hipError_t launch_emit(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
+                         hipStream_t stream);
+// Per-image prefix of min(counter, limit) into the header (which = 0 candidates, 1 keypoints).
+hipError_t launch_img_prefix(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int which,
+                             hipStream_t stream);
+hipError_t launch_refine(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
+                         hipStream_t stream);
+hipError_t launch_orient(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
+                         hipStream_t stream);
+hipError_t launch_ori_scan(char* ws, const HdrPtrs& hp, int n, const DevParams& p,
+                         hipStream_t stream);
+hipError_t launch_describe(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
+                         hipStream_t stream);
+
+}  // namespace sift

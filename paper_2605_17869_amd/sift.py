@@ -1,0 +1,305 @@
+"""Python binding of the C ABI in include/sift.h (argument marshalling only).
+
+Every step of extraction runs in the HIP library ``libsift_mi355x.so``; this
+module allocates device buffers with torch, passes raw pointers and the
+current HIP stream, and converts results.  It refuses to run when the library
+is missing: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, fields
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().with_name("libsift_mi355x.so")
+MAX_DSP = 16
+DESC_DIM = 128
+
+SIFT_OK = 0
+STATUS_NAMES = {
+    0: "SIFT_OK", 1: "SIFT_ERR_INVALID_ARG", 2: "SIFT_ERR_IMAGE_TOO_SMALL",
+    3: "SIFT_ERR_WORKSPACE_TOO_SMALL", 4: "SIFT_ERR_TOO_LARGE", 5: "SIFT_ERR_HIP",
+    6: "SIFT_ERR_NOT_SUPPORTED",
+}
+
+
+class SiftParams(ctypes.Structure):
+    _fields_ = [
+        ("n_octaves", ctypes.c_int32), ("n_scales", ctypes.c_int32), ("upsample", ctypes.c_int32),
+        ("sigma0", ctypes.c_float), ("sigma_in", ctypes.c_float),
+        ("contrast_threshold", ctypes.c_float), ("prefilter_ratio", ctypes.c_float),
+        ("edge_ratio", ctypes.c_float), ("border", ctypes.c_int32),
+        ("refine_iters", ctypes.c_int32), ("ori_bins", ctypes.c_int32),
+        ("ori_sigma_factor", ctypes.c_float), ("ori_radius_factor", ctypes.c_float),
+        ("ori_peak_ratio", ctypes.c_float), ("upright", ctypes.c_int32),
+        ("desc_width", ctypes.c_int32), ("desc_ori_bins", ctypes.c_int32),
+        ("desc_magnif", ctypes.c_float), ("desc_clamp", ctypes.c_float),
+        ("n_dsp", ctypes.c_int32), ("dsp_scales", ctypes.c_float * MAX_DSP),
+        ("rootsift", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
+        ("max_candidates", ctypes.c_int32),
+    ]
+
+
+class SiftOutput(ctypes.Structure):
+    _fields_ = [
+        ("keypoints", ctypes.c_void_p), ("descriptors", ctypes.c_void_p),
+        ("count", ctypes.c_void_p), ("n_found", ctypes.c_void_p),
+        ("n_candidates", ctypes.c_void_p), ("capacity", ctypes.c_int32),
+    ]
+
+
+class SiftStageStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+KEYPOINT_DTYPE = np.dtype([
+    ("x", "<f4"), ("y", "<f4"), ("sigma", "<f4"), ("angle", "<f4"), ("response", "<f4"),
+    ("octave", "<i4"), ("layer", "<i4"), ("ix", "<i4"), ("iy", "<i4"),
+    ("src_layer", "<i4"), ("src_iy", "<i4"), ("src_ix", "<i4"),
+])
+assert KEYPOINT_DTYPE.itemsize == 48
+
+# name -> (restype, argtypes)
+_SIGNATURES = {
+    "sift_params_default": (ctypes.c_int, [ctypes.POINTER(SiftParams)]),
+    "sift_create": (ctypes.c_int, [ctypes.POINTER(SiftParams), ctypes.POINTER(ctypes.c_void_p)]),
+    "sift_destroy": (None, [ctypes.c_void_p]),
+    "sift_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SiftParams)]),
+    "sift_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_size_t)]),
+    "sift_extract": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_size_t, ctypes.POINTER(SiftOutput), ctypes.c_void_p]),
+    "sift_batch_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                                 ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_int32),
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "sift_extract_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.POINTER(SiftOutput),
+                                          ctypes.c_void_p]),
+    "sift_workspace_level": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "sift_profile_start": (ctypes.c_int, []),
+    "sift_profile_stop": (ctypes.c_int, [ctypes.POINTER(SiftStageStat), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "sift_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sift_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+class SiftError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {detail}")
+        self.status = status
+
+
+def load_library():
+    """Load libsift_mi355x.so (built by ``python -m paper_2605_17869_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not LIB_PATH.exists():
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              f"`python -m paper_2605_17869_amd.build`")
+        # torch first: the library then binds to the HIP runtime torch already
+        # loaded (same soname), so the process holds a single runtime
+        import torch  # noqa: F401
+        lib = ctypes.CDLL(str(LIB_PATH))
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != SIFT_OK:
+        detail = load_library().sift_last_error().decode()
+        raise SiftError(status, where, detail)
+
+
+def make_params(settings: dict | None = None, **overrides) -> SiftParams:
+    """sift_params from the library defaults updated by ``settings`` (a dict
+    with sift_params field names; ``dsp_scales`` a sequence)."""
+    lib = load_library()
+    p = SiftParams()
+    _check(lib.sift_params_default(ctypes.byref(p)), "sift_params_default")
+    merged = dict(settings or {})
+    merged.update(overrides)
+    names = {f[0] for f in SiftParams._fields_}
+    for key, val in merged.items():
+        if key == "dsp_scales":
+            vals = [float(v) for v in val]
+            if not 1 <= len(vals) <= MAX_DSP:
+                raise ValueError("dsp_scales needs 1..16 entries")
+            p.n_dsp = len(vals)
+            for i in range(MAX_DSP):
+                p.dsp_scales[i] = vals[i] if i < len(vals) else 0.0
+        elif key in names:
+            setattr(p, key, type(getattr(p, key))(val))
+    return p
+
+
+@dataclass
+class Features:
+    """Device-resident results of one image (torch tensors on the GPU)."""
+    keypoints: object      # int32 [capacity, 12]: sift_keypoint records
+    descriptors: object    # float32 [capacity, 128]
+    counters: object       # int32 [3]: count, n_found, n_candidates
+
+    def host(self):
+        """(keypoints as a KEYPOINT_DTYPE array, descriptors, n_found, n_candidates)."""
+        cnt = self.counters.cpu().numpy()
+        n = int(cnt[0])
+        kp = self.keypoints[:n].cpu().numpy().copy().view(KEYPOINT_DTYPE).reshape(-1)
+        desc = self.descriptors[:n].cpu().numpy().copy()
+        return kp, desc, int(cnt[1]), int(cnt[2])
+
+
+def profile_start():
+    """Begin recording per-stage HIP events for every extraction."""
+    _check(load_library().sift_profile_start(), "sift_profile_start")
+
+
+def profile_stop() -> dict:
+    """Wait for recorded stages; {stage: (launches, ms, algorithmic bytes)}."""
+    arr = (SiftStageStat * 16)()
+    n = ctypes.c_int32()
+    _check(load_library().sift_profile_stop(arr, 16, ctypes.byref(n)), "sift_profile_stop")
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes)
+            for i in range(n.value)}
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Extractor:
+    """Handle around ``sift_create``; extraction allocates outputs and a
+    workspace with torch on the current device and enqueues on the current
+    (or given) stream."""
+
+    def __init__(self, settings: dict | None = None, **overrides):
+        self.lib = load_library()
+        self.params = make_params(settings, **overrides)
+        h = ctypes.c_void_p()
+        _check(self.lib.sift_create(ctypes.byref(self.params), ctypes.byref(h)), "sift_create")
+        self.handle = h
+        self._ws = None
+
+    def __del__(self):
+        lib, h = getattr(self, "lib", None), getattr(self, "handle", None)
+        if lib is not None and h is not None and h.value:
+            lib.sift_destroy(h)
+            self.handle = None
+
+    def workspace_size(self, height: int, width: int) -> int:
+        n = ctypes.c_size_t()
+        _check(self.lib.sift_workspace_size(self.handle, height, width, ctypes.byref(n)),
+               "sift_workspace_size")
+        return n.value
+
+    def batch_workspace_size(self, sizes) -> int:
+        n = len(sizes)
+        hs = (ctypes.c_int32 * n)(*[int(h) for h, _ in sizes])
+        ws = (ctypes.c_int32 * n)(*[int(w) for _, w in sizes])
+        out = ctypes.c_size_t()
+        _check(self.lib.sift_batch_workspace_size(self.handle, n, hs, ws, ctypes.byref(out)),
+               "sift_batch_workspace_size")
+        return out.value
+
+    def workspace(self, nbytes: int):
+        """A cached device workspace of at least nbytes."""
+        import torch
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def alloc_features(self, capacity: int | None = None) -> Features:
+        import torch
+        cap = int(self.params.max_keypoints if capacity is None else capacity)
+        return Features(torch.empty((max(cap, 1), 12), dtype=torch.int32, device="cuda"),
+                        torch.empty((max(cap, 1), DESC_DIM), dtype=torch.float32, device="cuda"),
+                        torch.zeros(3, dtype=torch.int32, device="cuda"))
+
+    @staticmethod
+    def _output(f: Features, capacity: int) -> SiftOutput:
+        base = f.counters.data_ptr()
+        return SiftOutput(f.keypoints.data_ptr(), f.descriptors.data_ptr(), base, base + 4,
+                          base + 8, capacity)
+
+    def extract(self, image, capacity: int | None = None, out: Features | None = None,
+                workspace=None, stream=None) -> Features:
+        """Enqueue extraction of one 2-D float32 CUDA tensor."""
+        import torch
+        if image.dim() != 2 or image.dtype != torch.float32 or not image.is_cuda:
+            raise ValueError("image must be a 2-D float32 CUDA tensor")
+        if image.stride(1) != 1:
+            raise ValueError("image rows must be contiguous")
+        h, w = image.shape
+        need = self.workspace_size(h, w)
+        ws = workspace if workspace is not None else self.workspace(need)
+        f = out if out is not None else self.alloc_features(capacity)
+        cap = f.keypoints.shape[0] if capacity is None else int(capacity)
+        o = self._output(f, cap)
+        _check(self.lib.sift_extract(self.handle, ctypes.c_void_p(image.data_ptr()), h, w,
+                                     image.stride(0), ctypes.c_void_p(ws.data_ptr()),
+                                     ws.numel() * ws.element_size(), ctypes.byref(o),
+                                     _stream_handle(stream)), "sift_extract")
+        return f
+
+    def extract_batch(self, images, capacity: int | None = None, outs=None, workspace=None,
+                      stream=None) -> list:
+        """Enqueue extraction of a list of 2-D float32 CUDA tensors in one batch."""
+        n = len(images)
+        import torch
+        for im in images:
+            if im.dim() != 2 or im.dtype != torch.float32 or not im.is_cuda or im.stride(1) != 1:
+                raise ValueError("images must be 2-D CUDA tensors with contiguous rows")
+        sizes = [tuple(im.shape) for im in images]
+        need = self.batch_workspace_size(sizes)
+        ws = workspace if workspace is not None else self.workspace(need)
+        feats = outs if outs is not None else [self.alloc_features(capacity) for _ in range(n)]
+        ptrs = (ctypes.c_void_p * n)(*[im.data_ptr() for im in images])
+        hs = (ctypes.c_int32 * n)(*[s[0] for s in sizes])
+        wss = (ctypes.c_int32 * n)(*[s[1] for s in sizes])
+        pitches = (ctypes.c_int64 * n)(*[im.stride(0) for im in images])
+        o = (SiftOutput * n)(*[self._output(f, f.keypoints.shape[0] if capacity is None
+                                            else int(capacity)) for f in feats])
+        _check(self.lib.sift_extract_batch(self.handle, n, ptrs, hs, wss, pitches,
+                                           ctypes.c_void_p(ws.data_ptr()),
+                                           ws.numel() * ws.element_size(), o,
+                                           _stream_handle(stream)), "sift_extract_batch")
+        return feats
+
+    def level(self, workspace, height: int, width: int, octave: int, level: int):
+        """Gaussian level (octave, level) of the last single-image extraction in
+        ``workspace`` as a float32 numpy array (L, not L - 0.5)."""
+        import torch
+        ptr = ctypes.c_void_p()
+        lh, lw, lp = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.sift_workspace_level(self.handle, height, width,
+                                             ctypes.c_void_p(workspace.data_ptr()), octave, level,
+                                             ctypes.byref(ptr), ctypes.byref(lh),
+                                             ctypes.byref(lw), ctypes.byref(lp)),
+               "sift_workspace_level")
+        off = ptr.value - workspace.data_ptr()
+        n = lh.value * lp.value
+        flat = workspace[off:off + 4 * n].view(torch.float32)
+        arr = flat.view(lh.value, lp.value)[:, :lw.value].cpu().numpy().astype(np.float64)
+        return arr + 0.5

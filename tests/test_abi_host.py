@@ -1,0 +1,163 @@
+"""C ABI on the host: the library loads, exports every declared entry point,
+its structs match the binding, and argument errors come back before any GPU
+work (CPU only: no call here reaches a kernel)."""
+import ctypes
+import re
+import subprocess
+from pathlib import Path
+
+import pytest
+
+from paper_2605_17869_amd import sift as S
+
+ROOT = Path(__file__).resolve().parents[1]
+HEADER = ROOT / "include" / "sift.h"
+
+
+def declared_functions():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sift_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = S.load_library()
+    names = declared_functions()
+    assert "sift_extract" in names and "sift_extract_batch" in names and "sift_create" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    nm = subprocess.run(["nm", "-D", "--defined-only", str(S.LIB_PATH)], capture_output=True,
+                        text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (sift_\w+)", nm))
+    assert set(names) <= exported
+
+
+PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "sift.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m))
+int main(void) {
+  printf("sift_params %zu\nsift_keypoint %zu\nsift_output %zu\nsift_stage_stat %zu\n",
+         sizeof(sift_params), sizeof(sift_keypoint), sizeof(sift_output), sizeof(sift_stage_stat));
+  F(sift_params, dsp_scales); F(sift_params, rootsift); F(sift_params, max_candidates);
+  F(sift_keypoint, octave); F(sift_keypoint, src_ix);
+  F(sift_output, n_candidates); F(sift_output, capacity);
+  F(sift_stage_stat, ms); F(sift_stage_stat, bytes);
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    src = tmp_path / "probe.c"
+    src.write_text(PROBE)
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", str(ROOT / "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True,
+                                                       text=True, check=True).stdout.splitlines())
+    assert int(out["sift_params"]) == ctypes.sizeof(S.SiftParams)
+    assert int(out["sift_keypoint"]) == S.KEYPOINT_DTYPE.itemsize == 48
+    assert int(out["sift_output"]) == ctypes.sizeof(S.SiftOutput)
+    assert int(out["sift_stage_stat"]) == ctypes.sizeof(S.SiftStageStat)
+    for key, val in out.items():
+        if "." not in key:
+            continue
+        t, m = key.split(".")
+        cls = {"sift_params": S.SiftParams, "sift_output": S.SiftOutput,
+               "sift_stage_stat": S.SiftStageStat}.get(t)
+        if cls is not None:
+            assert getattr(cls, m).offset == int(val), key
+        else:
+            assert S.KEYPOINT_DTYPE.fields[m][1] == int(val), key
+
+
+def test_defaults_and_parameter_validation():
+    p = S.make_params()
+    assert (p.n_octaves, p.n_scales, p.upsample, p.ori_bins, p.desc_width) == (4, 3, 0, 36, 4)
+    assert abs(p.contrast_threshold - 0.04 / 3) < 1e-8 and p.n_dsp == 1
+    lib = S.load_library()
+    h = ctypes.c_void_p()
+    for bad, code in [(dict(n_scales=0), 6), (dict(n_scales=7), 6), (dict(ori_bins=32), 6),
+                      (dict(border=0), 1), (dict(desc_width=3), 6), (dict(upsample=2), 1),
+                      (dict(n_octaves=12, upsample=1), 6), (dict(sigma0=9.0), 6),
+                      (dict(max_candidates=0), 1), (dict(ori_peak_ratio=1.5), 1)]:
+        pp = S.make_params(**bad)
+        assert lib.sift_create(ctypes.byref(pp), ctypes.byref(h)) == code, bad
+        assert lib.sift_last_error()
+    with pytest.raises(S.SiftError):
+        S.Extractor(n_scales=0)
+    ex = S.Extractor(dsp_scales=[0.5, 1.0, 2.0], rootsift=1)
+    q = S.SiftParams()
+    assert lib.sift_get_params(ex.handle, ctypes.byref(q)) == 0
+    assert q.n_dsp == 3 and q.rootsift == 1 and abs(q.dsp_scales[2] - 2.0) < 1e-7
+
+
+def test_workspace_size_rules():
+    ex = S.Extractor()
+    n = ex.workspace_size(480, 640)
+    # at least the pyramid: 6 levels of every octave, fp32
+    assert n > 6 * 4 * (480 * 640 + 240 * 320 + 120 * 160 + 60 * 80)
+    assert ex.workspace_size(481, 641) >= n
+    with pytest.raises(S.SiftError) as ei:
+        ex.workspace_size(100, 100)          # last octave 13x13 needs >= 13: ok
+        ex.workspace_size(96, 100)           # 12 rows at octave 3
+    assert ei.value.status == 2
+    with pytest.raises(S.SiftError) as ei:
+        ex.workspace_size(0, 100)
+    assert ei.value.status == 1
+    with pytest.raises(S.SiftError) as ei:
+        ex.workspace_size(40000, 100)
+    assert ei.value.status == 4
+    up = S.Extractor(upsample=1)
+    assert up.workspace_size(480, 640) > 2 * n
+    b = ex.batch_workspace_size([(480, 640), (300, 200)])
+    assert b > n
+
+
+def test_extract_argument_errors_return_before_any_launch():
+    lib = S.load_library()
+    ex = S.Extractor()
+    out = S.SiftOutput(1024, 2048, 4096, 0, 0, 10)
+    stream = ctypes.c_void_p()
+    # null image
+    st = lib.sift_extract(ex.handle, None, 480, 640, 640, ctypes.c_void_p(256), 1 << 30,
+                          ctypes.byref(out), stream)
+    assert st == 1
+    # pitch below width
+    st = lib.sift_extract(ex.handle, ctypes.c_void_p(512), 480, 640, 600, ctypes.c_void_p(256),
+                          1 << 30, ctypes.byref(out), stream)
+    assert st == 1
+    # misaligned workspace
+    st = lib.sift_extract(ex.handle, ctypes.c_void_p(512), 480, 640, 640, ctypes.c_void_p(260),
+                          1 << 30, ctypes.byref(out), stream)
+    assert st == 1
+    # workspace too small
+    st = lib.sift_extract(ex.handle, ctypes.c_void_p(512), 480, 640, 640, ctypes.c_void_p(256),
+                          1024, ctypes.byref(out), stream)
+    assert st == 3
+    # image too small for the octave count
+    st = lib.sift_extract(ex.handle, ctypes.c_void_p(512), 50, 640, 640, ctypes.c_void_p(256),
+                          1 << 30, ctypes.byref(out), stream)
+    assert st == 2
+    # null output pointers
+    bad = S.SiftOutput(0, 2048, 4096, 0, 0, 10)
+    st = lib.sift_extract(ex.handle, ctypes.c_void_p(512), 480, 640, 640, ctypes.c_void_p(256),
+                          1 << 30, ctypes.byref(bad), stream)
+    assert st == 1
+    # empty batch
+    st = lib.sift_extract_batch(ex.handle, 0, None, None, None, None, ctypes.c_void_p(256),
+                                1 << 30, None, stream)
+    assert st == 1
+
+
+def test_status_strings_and_profile_misuse():
+    lib = S.load_library()
+    assert lib.sift_status_string(0) == b"ok"
+    assert lib.sift_status_string(3) == b"workspace too small"
+    arr = (S.SiftStageStat * 4)()
+    n = ctypes.c_int32()
+    assert lib.sift_profile_stop(arr, 4, ctypes.byref(n)) == 1
+    assert lib.sift_profile_start() == 0
+    assert lib.sift_profile_stop(arr, 4, ctypes.byref(n)) == 0 and n.value == 0

@@ -1,0 +1,17 @@
+"""The device code contains no scalar memory access with a misaligned
+immediate offset (the scalar unit ignores the low bits of the base register,
+so such an access would read the wrong dword).  CPU only: compiles to gfx950
+assembly and inspects it."""
+from paper_2605_17869_amd import build
+
+
+def test_lint_flags_a_misaligned_immediate():
+    asm = "_Zk:\n\ts_load_dword s3, s[20:21], 0xff\n\ts_load_dwordx2 s[4:5], s[0:1], 0x10\n"
+    assert build.smem_misaligned(asm) == [("_Zk", "s_load_dword s3, s[20:21], 0xff")]
+
+
+def test_kernels_have_no_misaligned_scalar_offsets(tmp_path):
+    for src in sorted(build.CSRC.glob("*.hip")):
+        text = build.device_asm(src, tmp_path / (src.name + ".s"))
+        assert "s_load" in text
+        assert build.smem_misaligned(text) == []

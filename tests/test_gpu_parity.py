@@ -1,0 +1,183 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, plus
+determinism, batch invariance and cap semantics.  Needs an MI355X."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import parity
+from oracle import sift_oracle as so
+from paper_2605_17869_amd import synth
+from gpu_util import digest, extract, extract_batch, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+DENSITY = synth.BLOB_DENSITY
+
+
+def blobs(seed, h, w, density=DENSITY):
+    return synth.blob_image(seed, h, w, max(1, int(round(h * w * density))))
+
+
+def run_both(img, settings):
+    from paper_2605_17869_amd import Extractor
+    p = so.Params.from_settings(settings)
+    ref = oracle.sift(img, p, keep_octaves=True)
+    ex = Extractor(settings)
+    kp, desc, nf, nc = extract(ex, img)
+    return p, ref, kp, desc, nf, nc
+
+
+def assert_parity(p, ref, kp, desc, nf, nc, min_decisive=1):
+    rep = parity.compare(ref, kp, desc, p, so)
+    say(rep.summary())
+    for m in rep.mismatches[:10]:
+        say(f"  mismatch {m}")
+    assert rep.ok, rep.summary()
+    assert rep.decisive_ok >= min_decisive
+    assert nc == len(ref.log)
+    # n_found may differ only through marginal candidates
+    assert abs(nf - ref.n_found) <= 4 * (rep.marginal + rep.extra_marginal)
+    return rep
+
+
+def test_pyramid_levels_match_oracle():
+    from paper_2605_17869_amd import Extractor
+    wl = synth.workload(1)
+    img = wl.image(0)
+    p = so.Params.from_settings(wl.settings)
+    octs = so.scale_space(img, p)
+    ex = Extractor(wl.settings)
+    *_, ws = extract(ex, img, keep_ws=True)
+    worst = 0.0
+    for oc in octs:
+        for lv in range(p.n_scales + 3):
+            g = ex.level(ws, img.shape[0], img.shape[1], oc.o, lv)
+            assert g.shape == oc.L[lv].shape
+            worst = max(worst, float(np.max(np.abs(g - oc.L[lv]))))
+    say(f"max |L_gpu - L_oracle| = {worst:.3g}")
+    assert worst < 2e-6
+
+
+def test_upsampled_pyramid_matches_oracle():
+    from paper_2605_17869_amd import Extractor
+    settings = dict(synth.BASE_SETTINGS, upsample=1, n_octaves=3)
+    img = blobs(41, 133, 171)
+    p = so.Params.from_settings(settings)
+    octs = so.scale_space(img, p)
+    ex = Extractor(settings)
+    *_, ws = extract(ex, img, keep_ws=True)
+    worst = 0.0
+    for oc in octs:
+        for lv in range(p.n_scales + 3):
+            g = ex.level(ws, img.shape[0], img.shape[1], oc.o, lv)
+            worst = max(worst, float(np.max(np.abs(g - oc.L[lv]))))
+    say(f"upsampled: max |L_gpu - L_oracle| = {worst:.3g}")
+    assert worst < 2e-6
+
+
+def test_c1_keypoints_match_oracle():
+    wl = synth.workload(1)
+    img = wl.image(0)
+    say("workload 1: 640x480, 200 blobs")
+    rep = assert_parity(*run_both(img, wl.settings), min_decisive=50)
+    assert rep.max_err_xy <= parity.TOL_XY
+
+
+CASES = [
+    ("97x129 3 octaves", 97, 129, dict(n_octaves=3)),
+    ("130x75 ragged 2 octaves", 130, 75, dict(n_octaves=2)),
+    ("200x300 upsampled", 200, 300, dict(n_octaves=3, upsample=1)),
+    ("150x170 upright", 150, 170, dict(n_octaves=3, upright=1)),
+    ("160x220 paper DSP + RootSIFT", 160, 220,
+     dict(n_octaves=3, dsp_scales=(0.5, 1 / math.sqrt(2), 1.0, math.sqrt(2), 2.0), rootsift=1)),
+    ("160x220 K=10 DSP + RootSIFT", 160, 220, dict(n_octaves=3, dsp_scales=synth.dsp_linspace(),
+                                                   rootsift=1)),
+    ("120x140 s=2", 120, 140, dict(n_octaves=3, n_scales=2)),
+    ("180x200 s=4", 180, 200, dict(n_octaves=3, n_scales=4)),
+    ("104x104 minimum size, 4 octaves", 104, 104, dict(n_octaves=4)),
+    ("70x333 wide strip", 70, 333, dict(n_octaves=2)),
+]
+
+
+@pytest.mark.parametrize("name,h,w,extra", CASES, ids=[c[0] for c in CASES])
+def test_small_images_match_oracle(name, h, w, extra):
+    settings = dict(synth.BASE_SETTINGS, **extra)
+    img = blobs(1000 + h * 7 + w, h, w, density=3 * DENSITY)
+    say(f"case {name}")
+    assert_parity(*run_both(img, settings))
+
+
+def test_c2_image_full_size_matches_oracle():
+    wl = synth.workload(2, 1)
+    img = wl.image(0)
+    say("workload 2, image 0: 1024x768 with octave -1")
+    rep = assert_parity(*run_both(img, wl.settings), min_decisive=300)
+    assert rep.max_err_xy <= parity.TOL_XY
+
+
+def test_bitwise_identical_over_100_runs():
+    from paper_2605_17869_amd import Extractor
+    wl = synth.workload(1)
+    img = wl.image(0)
+    ex = Extractor(wl.settings)
+    first = None
+    for run in range(100):
+        kp, desc, nf, nc = extract(ex, img)
+        d = digest(kp, desc)
+        if first is None:
+            first = d
+            assert len(kp) > 50
+        assert d == first, f"run {run} differs"
+
+
+def test_batch_equals_single_image_bitwise():
+    from paper_2605_17869_amd import Extractor
+    sizes = [(97, 129), (130, 75), (480, 640), (104, 104), (333, 70)]
+    imgs = [blobs(77 + k, h, w, 3 * DENSITY) for k, (h, w) in enumerate(sizes)]
+    settings = dict(synth.BASE_SETTINGS, n_octaves=2)
+    ex = Extractor(settings)
+    singles = [extract(ex, im) for im in imgs]
+    batched = extract_batch(ex, imgs)
+    shuffled = extract_batch(ex, imgs[::-1])[::-1]
+    for k in range(len(imgs)):
+        a, b, c = singles[k], batched[k], shuffled[k]
+        assert digest(a[0], a[1]) == digest(b[0], b[1]) == digest(c[0], c[1]), k
+        assert a[2:] == b[2:] == c[2:]
+
+
+def test_keypoint_cap_and_capacity():
+    from paper_2605_17869_amd import Extractor
+    wl = synth.workload(1)
+    img = wl.image(0)
+    full = extract(Extractor(wl.settings), img)
+    assert len(full[0]) > 40
+    capped = extract(Extractor(dict(wl.settings, max_keypoints=25)), img)
+    assert len(capped[0]) == 25 and capped[2] == full[2]
+    assert digest(capped[0], capped[1]) == digest(full[0][:25], full[1][:25])
+    small = extract(Extractor(wl.settings), img, capacity=7)
+    assert len(small[0]) == 7 and small[2] == full[2]
+    assert digest(small[0], small[1]) == digest(full[0][:7], full[1][:7])
+
+
+def test_candidate_cap_keeps_canonical_prefix():
+    from paper_2605_17869_amd import Extractor
+    wl = synth.workload(1)
+    img = wl.image(0)
+    full = extract(Extractor(wl.settings), img)
+    cut = extract(Extractor(dict(wl.settings, max_candidates=40)), img)
+    assert cut[3] == full[3] > 40
+    src = lambda kp: [(int(k["octave"]), int(k["src_layer"]), int(k["src_iy"]), int(k["src_ix"]))
+                      for k in kp]
+    n = len(cut[0])
+    assert 0 < n < len(full[0])
+    assert src(cut[0]) == src(full[0])[:n]
+    assert digest(cut[0], cut[1]) == digest(full[0][:n], full[1][:n])
+
+
+def test_flat_image_has_no_keypoints():
+    from paper_2605_17869_amd import Extractor
+    img = np.full((120, 160), 0.42, dtype=np.float32)
+    kp, desc, nf, nc = extract(Extractor(dict(synth.BASE_SETTINGS, n_octaves=3)), img)
+    assert len(kp) == 0 and nf == 0 and nc == 0
