@@ -29,6 +29,43 @@ sys.path.insert(0, ROOT)
 from paper_2605_17869_amd import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2605_17869_amd", "csrc", "sift_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blur_hbm_traffic_w2.txt")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per blur launch from the committed counter summary, or None
+    when it is missing or was taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            fields = dict(l.split(":", 1) for l in f.read().splitlines() if ":" in l)
+    except OSError:
+        return None
+    if fields.get("kernel_source_sha256", "").strip() != kernel_source_hash():
+        return None
+    try:
+        return int(fields["hbm_bytes_per_launch"].strip())
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib: int, reps: int):
+    """A plain elementwise pass of known size (read mib MiB, write mib MiB),
+    the yardstick for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "neg", "bytes_read_per_dispatch": 4 * n,
+                      "bytes_written_per_dispatch": 4 * n, "dispatches": reps}), flush=True)
 
 
 def _gen(args):
@@ -62,12 +99,19 @@ def main():
     ap.add_argument("--per-image-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--tile-rows", type=int, default=0, help="blur tile height (0: library choice)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain elementwise pass over MIB MiB (counter yardstick)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               f"(images shard across GPUs with no exchange; run one process per GPU)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, max(1, args.steps))
+        return
 
     import torch
     import paper_2605_17869_amd as sm
@@ -80,7 +124,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     d_imgs = [torch.from_numpy(im).to(dev) for im in imgs]
-    ex = sm.Extractor(wl.settings)
+    settings = dict(wl.settings, tile_rows=args.tile_rows)
+    ex = sm.Extractor(settings)
     sizes = [tuple(im.shape) for im in imgs]
     ws = torch.empty(ex.batch_workspace_size(sizes), dtype=torch.uint8, device=dev)
     outs = [ex.alloc_features() for _ in range(n)]
@@ -106,26 +151,28 @@ def main():
     batch_host = [f.host() for f in outs]
 
     # plain per-image path on the same images
-    ws1 = torch.empty(max(ex.workspace_size(*s) for s in sizes), dtype=torch.uint8, device=dev)
-    outs1 = [ex.alloc_features() for _ in range(n)]
+    ms1, identical = None, None
+    if args.per_image_steps > 0:
+        ws1 = torch.empty(max(ex.workspace_size(*s) for s in sizes), dtype=torch.uint8, device=dev)
+        outs1 = [ex.alloc_features() for _ in range(n)]
 
-    def per_image_step():
-        for k in range(n):
-            ex.extract(d_imgs[k], out=outs1[k], workspace=ws1, stream=stream)
+        def per_image_step():
+            for k in range(n):
+                ex.extract(d_imgs[k], out=outs1[k], workspace=ws1, stream=stream)
 
-    per_image_step()
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.per_image_steps):
         per_image_step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms1 = e0.elapsed_time(e1) / args.per_image_steps
-    single_host = [f.host() for f in outs1]
-    identical = all(digest(a[0], a[1]) == digest(b[0], b[1]) and a[2:] == b[2:]
-                    for a, b in zip(batch_host, single_host))
-    print(f"[bench] per-image: {ms1:.3f} ms/step, identical={identical}", file=sys.stderr,
-          flush=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.per_image_steps):
+            per_image_step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms1 = e0.elapsed_time(e1) / args.per_image_steps
+        single_host = [f.host() for f in outs1]
+        identical = all(digest(a[0], a[1]) == digest(b[0], b[1]) and a[2:] == b[2:]
+                        for a, b in zip(batch_host, single_host))
+        print(f"[bench] per-image: {ms1:.3f} ms/step, identical={identical}", file=sys.stderr,
+              flush=True)
 
     # stage breakdown with HIP events on the extraction stream
     stages = {}
@@ -145,9 +192,10 @@ def main():
             achieved = (bbytes / launches) / (bms / launches * 1e-3) / 1e9
             roofline = {"kernel": "k_blur (separable Gaussian level, all radii)", "bound": "hbm",
                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                         "avg_launch_us": round(1e3 * bms / launches, 2),
-                        "bytes_per_launch": round(bbytes / launches)}
+                        "bytes_per_launch": round(bbytes / launches),
+                        "kernel_source_sha256": kernel_source_hash()}
         print(f"[bench] stages: {json.dumps(stages)}", file=sys.stderr, flush=True)
 
     cpu = None
@@ -178,11 +226,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "images": n, "image_size": f"{sizes[0][1]}x{sizes[0][0]}",
-                   "upsample": wl.settings["upsample"], "octaves": wl.settings["n_octaves"] +
+                   "tile_rows": args.tile_rows, "upsample": wl.settings["upsample"], "octaves": wl.settings["n_octaves"] +
                    wl.settings["upsample"], "parallelism": "none (one GPU)"},
         "mpix_per_s": round(mpix / (ms * 1e-3), 2),
-        "per_image_path": {"images_per_s": round(n / (ms1 * 1e-3), 2), "ms_per_step": round(ms1, 4)},
-        "batched_vs_per_image": round(ms1 / ms, 3),
+        "per_image_path": ({"images_per_s": round(n / (ms1 * 1e-3), 2),
+                            "ms_per_step": round(ms1, 4)} if ms1 else None),
+        "batched_vs_per_image": round(ms1 / ms, 3) if ms1 else None,
         "bitwise_identical_batched_vs_per_image": identical,
         "keypoints_per_image": round(n_kp / n, 1),
         "stages": stages,

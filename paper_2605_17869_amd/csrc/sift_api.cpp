@@ -35,7 +35,15 @@ sift_status fail(sift_status st, const char* fmt, ...) {
 
 constexpr int kMaxSide = 32768;    // per input dimension
 constexpr int kMaxBatch = 4096;
-constexpr int kBlurTileH = 32;
+
+// Tile height of a blur level: the caller's choice, else the library's.
+int blur_tile_h(int tile_rows, int radius) {
+  int th = tile_rows ? tile_rows : 32;
+  if (th == 64 && radius > 16) th = 32;
+  return th;
+}
+
+int tile_class(int th) { return th == 16 ? 0 : th == 32 ? 1 : 2; }
 
 // Sampled Gaussian exp(-t^2 / (2 sigma^2)), t = -R..R, R = ceil(4 sigma),
 // normalised by its double-precision sum and rounded to float.
@@ -101,6 +109,8 @@ sift_status validate_params(const sift_params& p) {
   if (p.max_keypoints < 0) return fail(SIFT_ERR_INVALID_ARG, "max_keypoints must be >= 0");
   if (p.max_candidates < 1 || p.max_candidates > (1 << 24))
     return fail(SIFT_ERR_INVALID_ARG, "max_candidates must be in 1..2^24");
+  if (p.tile_rows != 0 && p.tile_rows != 16 && p.tile_rows != 32 && p.tile_rows != 64)
+    return fail(SIFT_ERR_INVALID_ARG, "tile_rows must be 0, 16, 32 or 64");
   return SIFT_OK;
 }
 
@@ -227,7 +237,6 @@ sift_status sift_create(const sift_params* p, sift_handle** out) {
   d.max_kp = p->max_keypoints;
   d.max_cand = p->max_candidates;
   d.n_dsp = p->n_dsp;
-  d.blur_th = kBlurTileH;
   d.sigma0 = p->sigma0;
   d.contrast_thr = p->contrast_threshold;
   d.pre_thr = p->prefilter_ratio * p->contrast_threshold;
@@ -321,7 +330,7 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
 
   // image table, a chunk of entries per launch
   int prec = prof_begin(kStSetup, 0.0, stream);
-  std::vector<int64_t> tiles(p.n_oct, 0);
+  std::vector<int64_t> tiles(kNumTileH * p.n_oct, 0);
   std::vector<int64_t> pixels(p.n_oct, 0);
   int64_t input_px = 0;
   int64_t bands = 0;
@@ -346,7 +355,7 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
     for (int k = 0; k < p.n_oct; ++k) {
       int hk, wk;
       octave_dims(heights[i], widths[i], p.upsample, k, &hk, &wk);
-      tiles[k] += cdiv(wk, kTileW) * cdiv(hk, p.blur_th);
+      for (int c = 0; c < kNumTileH; ++c) tiles[c * p.n_oct + k] += cdiv(wk, kTileW) * cdiv(hk, tile_h_of(c));
       pixels[k] += (int64_t)hk * wk;
     }
     input_px += (int64_t)heights[i] * widths[i];
@@ -357,8 +366,8 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
       chunk.count = 0;
     }
   }
-  for (int k = 0; k < p.n_oct; ++k)
-    if (tiles[k] > INT32_MAX) return fail(SIFT_ERR_TOO_LARGE, "batch has too many tiles");
+  for (int64_t t : tiles)
+    if (t > INT32_MAX - kXcds) return fail(SIFT_ERR_TOO_LARGE, "batch has too many tiles");
   if (bands > INT32_MAX) return fail(SIFT_ERR_TOO_LARGE, "batch has too many bands");
   if ((st = check_hip(launch_finalize(hp, n, p, stream), "finalize")) != SIFT_OK) return st;
   prof_end(prec, stream);
@@ -368,15 +377,17 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
     for (int lv = (k == 0 ? 0 : 1); lv <= p.s + 2; ++lv) {
       BlurArgs a;
       std::memset(&a, 0, sizeof a);
+      const Taps& t = lv == 0 ? h->init : h->inc[lv - 1];
+      const int th = blur_tile_h(h->params.tile_rows, t.radius);
+      const int cls = tile_class(th);
       a.ws = ws;
       a.table = hp.table;
-      a.tile_prefix = hp.tile_prefix + (int64_t)k * (n + 1);
+      a.tile_prefix = hp.tile_prefix + (int64_t)(cls * kMaxOct + k) * (n + 1);
       a.n = n;
       a.k = k;
       a.dst_level = lv;
-      a.th = p.blur_th;
+      a.th = th;
       a.p = p;
-      const Taps& t = lv == 0 ? h->init : h->inc[lv - 1];
       if (lv == 0) a.mode = p.upsample ? kSrcUpsample : kSrcImage;
       else if (lv == 1 && k > 0) a.mode = kSrcDown;
       else a.mode = kSrcLevel;
@@ -387,7 +398,8 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
       if (lv == 0 && p.upsample) bytes = 4.0 * pixels[k] + 4.0 * input_px;
       if (a.mode == kSrcDown) bytes += 4.0 * pixels[k];
       prec = prof_begin(kStBlur, bytes, stream);
-      if ((st = check_hip(launch_blur(a, t.radius, (int)tiles[k], stream), "blur")) != SIFT_OK) return st;
+      const int grid = (int)((tiles[cls * p.n_oct + k] + kXcds - 1) / kXcds * kXcds);
+      if ((st = check_hip(launch_blur(a, t.radius, grid, stream), "blur")) != SIFT_OK) return st;
       prof_end(prec, stream);
     }
   }

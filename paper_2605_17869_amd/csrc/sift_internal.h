@@ -22,6 +22,8 @@ constexpr int kMaxOct = 12;        // octaves including octave -1
 constexpr int kMaxScales = 6;      // n_scales supported by the detector
 constexpr int kMaxRadius = 24;     // largest Gaussian radius ceil(4 sigma)
 constexpr int kTileW = 64;         // blur tile width (one wave of columns)
+constexpr int kNumTileH = 3;       // blur tile heights 16, 32, 64
+constexpr int kXcds = 8;           // work-groups are dealt round-robin to the XCDs
 constexpr int kBand = 16;          // rows per detection band
 constexpr int kSeg = 62;           // output columns per 64-lane detection segment
 constexpr int kOriBins = 36;
@@ -187,9 +189,11 @@ struct ImgEntry {
 };
 
 // Workspace header: image table and per-octave tile prefix sums.
+SIFT_HD int tile_h_of(int cls) { return 16 << cls; }
+
 struct Header {
   int64_t table;           // ImgEntry[n]
-  int64_t tile_prefix;     // int32 [n_oct][n + 1]
+  int64_t tile_prefix;     // int32 [kNumTileH][kMaxOct][n + 1]
   int64_t band_prefix;     // int32 [n + 1]
   int64_t cand_prefix;     // int32 [n + 1]: refined candidates per image
   int64_t kp_prefix;       // int32 [n + 1]: described keypoints per image
@@ -203,7 +207,7 @@ struct Header {
 // aligned, which the scalar memory unit does not honour).
 struct HdrPtrs {
   const ImgEntry* table;   // ImgEntry[n]
-  int* tile_prefix;        // int32 [n_oct][n + 1]
+  int* tile_prefix;        // int32 [kNumTileH][kMaxOct][n + 1]
   int* band_prefix;        // int32 [n + 1]
   int* cand_prefix;        // int32 [n + 1]
   int* kp_prefix;          // int32 [n + 1]
@@ -214,7 +218,7 @@ SIFT_HD void make_header(int n, Header* hd) {
   hd->table = off;
   off = align_up(off + (int64_t)n * (int64_t)sizeof(ImgEntry), 256);
   hd->tile_prefix = off;
-  off = align_up(off + (int64_t)kMaxOct * (n + 1) * 4, 256);
+  off = align_up(off + (int64_t)kNumTileH * kMaxOct * (n + 1) * 4, 256);
   hd->band_prefix = off;
   off = align_up(off + (int64_t)(n + 1) * 4, 256);
   hd->cand_prefix = off;
@@ -227,7 +231,7 @@ SIFT_HD void make_header(int n, Header* hd) {
 // Settings the kernels read (a by-value kernel argument).
 struct DevParams {
   int n_oct, o0, s, upsample, border, refine_iters, upright, rootsift;
-  int max_kp, max_cand, n_dsp, blur_th;
+  int max_kp, max_cand, n_dsp, pad0;
   float sigma0, contrast_thr, pre_thr, edge_ratio;
   float ori_sigma_factor, ori_radius_factor, ori_peak_ratio;
   float desc_magnif, desc_clamp;
@@ -261,12 +265,12 @@ enum BlurSrc { kSrcImage = 0, kSrcUpsample = 1, kSrcLevel = 2, kSrcDown = 3 };
 struct BlurArgs {
   char* ws;
   const ImgEntry* table;
-  const int* tile_prefix;   // prefix of this octave: n + 1 entries
+  const int* tile_prefix;   // tiles of this octave and tile height: n + 1 entries
   int n;
   int k;            // octave slot
   int dst_level;    // level written
   int mode;         // BlurSrc
-  int th;           // tile height
+  int th;           // tile height (16, 32 or 64)
   DevParams p;
   float taps[2 * kMaxRadius + 1];
 };

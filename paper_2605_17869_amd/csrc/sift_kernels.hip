@@ -115,17 +115,21 @@ __global__ void k_finalize(HdrPtrs hp, int n, DevParams p) {
   const ImgEntry* tab = hp.table;
   int* tp = hp.tile_prefix;
   int* bp = hp.band_prefix;
-  const int k = threadIdx.x;
-  if (k < p.n_oct) {
+  const int t = threadIdx.x;
+  if (t < kNumTileH * p.n_oct) {
+    // tile prefix for tile-height class t / n_oct, octave t % n_oct
+    const int cls = t / p.n_oct, k = t - cls * p.n_oct;
+    const int th = tile_h_of(cls);
+    int* out = tp + (cls * kMaxOct + k) * (n + 1);
     int acc = 0;
-    tp[k * (n + 1)] = 0;
+    out[0] = 0;
     for (int i = 0; i < n; ++i) {
       int hk, wk;
       octave_dims(tab[i].h, tab[i].w, p.upsample, k, &hk, &wk);
-      acc += cdiv(wk, kTileW) * cdiv(hk, p.blur_th);
-      tp[k * (n + 1) + i + 1] = acc;
+      acc += cdiv(wk, kTileW) * cdiv(hk, th);
+      out[i + 1] = acc;
     }
-  } else if (k == p.n_oct) {
+  } else if (t == kNumTileH * p.n_oct) {
     const LayoutCfg lc = layout_cfg(p);
     int acc = 0;
     bp[0] = 0;
@@ -145,6 +149,11 @@ __global__ void k_finalize(HdrPtrs hp, int n, DevParams p) {
 // whatever the tile shape.  Levels are held relative to mid-grey (L - 0.5):
 // the blur is linear with unit-sum taps, so this changes no difference of
 // levels and keeps fp32 rounding error proportional to |L - 0.5|.
+//
+// Work-groups are dealt round-robin to the 8 XCDs, each with its own L2; the
+// grid is a multiple of 8 and group b takes tile (b % 8) * (grid / 8) + b / 8,
+// so every XCD sweeps one contiguous run of tiles and neighbouring tiles find
+// their shared halo rows in the same L2.
 template <int R, int TH>
 __global__ __launch_bounds__(256) void k_blur(BlurArgs a) {
   constexpr int IW = kTileW + 2 * R;
@@ -158,7 +167,9 @@ __global__ __launch_bounds__(256) void k_blur(BlurArgs a) {
   __shared__ float s_h[IH * HS];
 
   const int* tp = a.tile_prefix;
-  const int item = blockIdx.x;
+  const int per_xcd = gridDim.x / kXcds;
+  const int item = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
+  if (item >= tp[a.n]) return;
   const int img = find_owner(tp, a.n, item);
   const int local = item - tp[img];
   const ImgEntry e = a.table[img];
@@ -895,24 +906,33 @@ hipError_t launch_finalize(const HdrPtrs& hp, int n, const DevParams& p, hipStre
 
 typedef void (*BlurKernel)(BlurArgs);
 
-template <int TH>
-static BlurKernel blur_kernel(int radius) {
-  switch (radius) {
-#define SIFT_BLUR_CASE(RR) case RR: return k_blur<RR, TH>;
-    SIFT_BLUR_CASE(1) SIFT_BLUR_CASE(2) SIFT_BLUR_CASE(3) SIFT_BLUR_CASE(4)
-    SIFT_BLUR_CASE(5) SIFT_BLUR_CASE(6) SIFT_BLUR_CASE(7) SIFT_BLUR_CASE(8)
-    SIFT_BLUR_CASE(9) SIFT_BLUR_CASE(10) SIFT_BLUR_CASE(11) SIFT_BLUR_CASE(12)
-    SIFT_BLUR_CASE(13) SIFT_BLUR_CASE(14) SIFT_BLUR_CASE(15) SIFT_BLUR_CASE(16)
-    SIFT_BLUR_CASE(17) SIFT_BLUR_CASE(18) SIFT_BLUR_CASE(19) SIFT_BLUR_CASE(20)
-    SIFT_BLUR_CASE(21) SIFT_BLUR_CASE(22) SIFT_BLUR_CASE(23) SIFT_BLUR_CASE(24)
-#undef SIFT_BLUR_CASE
-    default: return nullptr;
+#define SIFT_BLUR_CASES_16(TH)                                                           \
+  SIFT_BLUR_CASE(1, TH) SIFT_BLUR_CASE(2, TH) SIFT_BLUR_CASE(3, TH) SIFT_BLUR_CASE(4, TH)     \
+  SIFT_BLUR_CASE(5, TH) SIFT_BLUR_CASE(6, TH) SIFT_BLUR_CASE(7, TH) SIFT_BLUR_CASE(8, TH)     \
+  SIFT_BLUR_CASE(9, TH) SIFT_BLUR_CASE(10, TH) SIFT_BLUR_CASE(11, TH) SIFT_BLUR_CASE(12, TH)  \
+  SIFT_BLUR_CASE(13, TH) SIFT_BLUR_CASE(14, TH) SIFT_BLUR_CASE(15, TH) SIFT_BLUR_CASE(16, TH)
+#define SIFT_BLUR_CASES_24(TH)                                                           \
+  SIFT_BLUR_CASES_16(TH)                                                                   \
+  SIFT_BLUR_CASE(17, TH) SIFT_BLUR_CASE(18, TH) SIFT_BLUR_CASE(19, TH) SIFT_BLUR_CASE(20, TH) \
+  SIFT_BLUR_CASE(21, TH) SIFT_BLUR_CASE(22, TH) SIFT_BLUR_CASE(23, TH) SIFT_BLUR_CASE(24, TH)
+#define SIFT_BLUR_CASE(RR, TH) \
+  case RR: return k_blur<RR, TH>;
+
+static BlurKernel blur_kernel(int radius, int th) {
+  if (th == 16) {
+    switch (radius) { SIFT_BLUR_CASES_24(16) default: return nullptr; }
+  } else if (th == 32) {
+    switch (radius) { SIFT_BLUR_CASES_24(32) default: return nullptr; }
+  } else if (th == 64) {
+    // 64-row tiles stay within 64 KiB of LDS up to radius 16
+    switch (radius) { SIFT_BLUR_CASES_16(64) default: return nullptr; }
   }
+  return nullptr;
 }
+#undef SIFT_BLUR_CASE
 
 hipError_t launch_blur(const BlurArgs& a, int radius, int grid, hipStream_t stream) {
-  BlurKernel fn = nullptr;
-  if (a.th == 32) fn = blur_kernel<32>(radius);
+  BlurKernel fn = blur_kernel(radius, a.th);
   if (!fn) return hipErrorInvalidValue;
   return launch(fn, dim3(grid), dim3(256), stream, a);
 }

@@ -38,7 +38,7 @@ class SiftParams(ctypes.Structure):
         ("desc_magnif", ctypes.c_float), ("desc_clamp", ctypes.c_float),
         ("n_dsp", ctypes.c_int32), ("dsp_scales", ctypes.c_float * MAX_DSP),
         ("rootsift", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
-        ("max_candidates", ctypes.c_int32),
+        ("max_candidates", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
     ]
 
 

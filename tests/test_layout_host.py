@@ -64,7 +64,7 @@ int main() {
   for (int n = 1; n < 300; n += 37) {
     Header hd; make_header(n, &hd); int h = n, w = 0;
     CHECK(hd.tile_prefix >= (int64_t)n * (int64_t)sizeof(ImgEntry));
-    CHECK(hd.band_prefix >= hd.tile_prefix + (int64_t)kMaxOct * (n + 1) * 4);
+    CHECK(hd.band_prefix >= hd.tile_prefix + (int64_t)kNumTileH * kMaxOct * (n + 1) * 4);
     CHECK(hd.cand_prefix >= hd.band_prefix + (n + 1) * 4);
     CHECK(hd.kp_prefix >= hd.cand_prefix + (n + 1) * 4);
     CHECK(hd.bytes >= hd.kp_prefix + (n + 1) * 4 && hd.bytes % 256 == 0);
