@@ -78,8 +78,9 @@ typedef struct {
   int32_t rootsift;           /* 0: 1 applies L1 normalisation then sqrt */
   int32_t max_keypoints;      /* 65536: keypoints kept per image (canonical order) */
   int32_t max_candidates;     /* 65536: detections refined per image (canonical order) */
-  int32_t tile_rows;          /* 0: library choice; 16, 32 or 64 rows per blur tile.  Any
-                                 value gives bit-identical results (tuning only) */
+  int32_t tile_rows;          /* 0: library choice; else 64, 128, 256 or 512 rows per blur
+                                 work-group.  Any value gives bit-identical results (tuning
+                                 only) */
 } sift_params;
 
 /* One keypoint, 48 bytes.  Keypoints of an image come in canonical order:

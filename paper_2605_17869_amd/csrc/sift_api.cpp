@@ -36,14 +36,20 @@ sift_status fail(sift_status st, const char* fmt, ...) {
 constexpr int kMaxSide = 32768;    // per input dimension
 constexpr int kMaxBatch = 4096;
 
-// Tile height of a blur level: the caller's choice, else the library's.
-int blur_tile_h(int tile_rows, int radius) {
-  int th = tile_rows ? tile_rows : 32;
-  if (th == 64 && radius > 16) th = 32;
-  return th;
-}
+// Chunk height class of a blur level: the caller's choice, else the tallest
+// chunk that still gives at least kBlurTargetGroups work-groups (enough to
+// fill every CU several times over), else the shortest.
+constexpr int kBlurTargetGroups = 2048;
 
-int tile_class(int th) { return th == 16 ? 0 : th == 32 ? 1 : 2; }
+int blur_class(int tile_rows, const int64_t* tiles_of_class) {
+  if (tile_rows) {
+    for (int c = 0; c < kNumTileH; ++c)
+      if (tile_h_of(c) == tile_rows) return c;
+  }
+  for (int c = kNumTileH - 1; c > 0; --c)
+    if (tiles_of_class[c] >= kBlurTargetGroups) return c;
+  return 0;
+}
 
 // Sampled Gaussian exp(-t^2 / (2 sigma^2)), t = -R..R, R = ceil(4 sigma),
 // normalised by its double-precision sum and rounded to float.
@@ -109,8 +115,9 @@ sift_status validate_params(const sift_params& p) {
   if (p.max_keypoints < 0) return fail(SIFT_ERR_INVALID_ARG, "max_keypoints must be >= 0");
   if (p.max_candidates < 1 || p.max_candidates > (1 << 24))
     return fail(SIFT_ERR_INVALID_ARG, "max_candidates must be in 1..2^24");
-  if (p.tile_rows != 0 && p.tile_rows != 16 && p.tile_rows != 32 && p.tile_rows != 64)
-    return fail(SIFT_ERR_INVALID_ARG, "tile_rows must be 0, 16, 32 or 64");
+  if (p.tile_rows != 0 && p.tile_rows != 64 && p.tile_rows != 128 && p.tile_rows != 256 &&
+      p.tile_rows != 512)
+    return fail(SIFT_ERR_INVALID_ARG, "tile_rows must be 0, 64, 128, 256 or 512");
   return SIFT_OK;
 }
 
@@ -330,7 +337,7 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
 
   // image table, a chunk of entries per launch
   int prec = prof_begin(kStSetup, 0.0, stream);
-  std::vector<int64_t> tiles(kNumTileH * p.n_oct, 0);
+  std::vector<int64_t> tiles(kNumTileH * p.n_oct, 0);   // [octave][class]
   std::vector<int64_t> pixels(p.n_oct, 0);
   int64_t input_px = 0;
   int64_t bands = 0;
@@ -355,7 +362,7 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
     for (int k = 0; k < p.n_oct; ++k) {
       int hk, wk;
       octave_dims(heights[i], widths[i], p.upsample, k, &hk, &wk);
-      for (int c = 0; c < kNumTileH; ++c) tiles[c * p.n_oct + k] += cdiv(wk, kTileW) * cdiv(hk, tile_h_of(c));
+      for (int c = 0; c < kNumTileH; ++c) tiles[k * kNumTileH + c] += cdiv(wk, kTileW) * cdiv(hk, tile_h_of(c));
       pixels[k] += (int64_t)hk * wk;
     }
     input_px += (int64_t)heights[i] * widths[i];
@@ -378,8 +385,8 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
       BlurArgs a;
       std::memset(&a, 0, sizeof a);
       const Taps& t = lv == 0 ? h->init : h->inc[lv - 1];
-      const int th = blur_tile_h(h->params.tile_rows, t.radius);
-      const int cls = tile_class(th);
+      const int cls = blur_class(h->params.tile_rows, &tiles[k * kNumTileH]);
+      const int th = tile_h_of(cls);
       a.ws = ws;
       a.table = hp.table;
       a.tile_prefix = hp.tile_prefix + (int64_t)(cls * kMaxOct + k) * (n + 1);
@@ -398,7 +405,7 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
       if (lv == 0 && p.upsample) bytes = 4.0 * pixels[k] + 4.0 * input_px;
       if (a.mode == kSrcDown) bytes += 4.0 * pixels[k];
       prec = prof_begin(kStBlur, bytes, stream);
-      const int grid = (int)((tiles[cls * p.n_oct + k] + kXcds - 1) / kXcds * kXcds);
+      const int grid = (int)((tiles[k * kNumTileH + cls] + kXcds - 1) / kXcds * kXcds);
       if ((st = check_hip(launch_blur(a, t.radius, grid, stream), "blur")) != SIFT_OK) return st;
       prof_end(prec, stream);
     }

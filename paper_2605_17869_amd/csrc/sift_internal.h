@@ -21,8 +21,9 @@ namespace sift {
 constexpr int kMaxOct = 12;        // octaves including octave -1
 constexpr int kMaxScales = 6;      // n_scales supported by the detector
 constexpr int kMaxRadius = 24;     // largest Gaussian radius ceil(4 sigma)
-constexpr int kTileW = 64;         // blur tile width (one wave of columns)
-constexpr int kNumTileH = 3;       // blur tile heights 16, 32, 64
+constexpr int kTileW = 128;        // blur strip width (output columns of one work-group)
+constexpr int kBlurRows = 16;      // rows a blur work-group advances per step
+constexpr int kNumTileH = 4;       // blur chunk heights 64, 128, 256, 512
 constexpr int kXcds = 8;           // work-groups are dealt round-robin to the XCDs
 constexpr int kBand = 16;          // rows per detection band
 constexpr int kSeg = 62;           // output columns per 64-lane detection segment
@@ -189,7 +190,7 @@ struct ImgEntry {
 };
 
 // Workspace header: image table and per-octave tile prefix sums.
-SIFT_HD int tile_h_of(int cls) { return 16 << cls; }
+SIFT_HD int tile_h_of(int cls) { return 64 << cls; }
 
 struct Header {
   int64_t table;           // ImgEntry[n]
@@ -270,7 +271,7 @@ struct BlurArgs {
   int k;            // octave slot
   int dst_level;    // level written
   int mode;         // BlurSrc
-  int th;           // tile height (16, 32 or 64)
+  int th;           // chunk height (64, 128, 256 or 512 rows)
   DevParams p;
   float taps[2 * kMaxRadius + 1];
 };
