@@ -29,13 +29,18 @@ sys.path.insert(0, ROOT)
 from paper_2605_17869_amd import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2605_17869_amd", "csrc", "sift_kernels.hip")
+# sources of the blur kernel: a traffic figure holds only while they are unchanged
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_17869_amd", "csrc", f)
+                  for f in ("sift_blur.hip", "sift_device.h", "sift_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blur_hbm_traffic_w2.txt")
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():

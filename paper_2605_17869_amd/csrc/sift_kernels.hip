@@ -4,111 +4,17 @@
 // tables over the images of the batch, so one image goes through exactly
 // the same per-pixel and per-keypoint arithmetic whether it is extracted
 // alone or with others.  No two lanes ever add floats into the same memory
-// location (histograms keep one column per lane); every sum has an order
-// fixed in this source, which makes the output bit-identical from run to run.  The file is built with -ffp-contract=off: every fused
+// location in one instruction (histograms keep columns that lanes own); every
+// sum has an order fixed in this source, which makes the output bit-identical
+// from run to run.  The file is built with -ffp-contract=off: every fused
 // multiply-add below is written out explicitly.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
-#include "sift_internal.h"
+#include "sift_device.h"
 #include "sift_launch.h"
 
 namespace sift {
-
-constexpr float kTwoPi = 6.28318530717958647692f;
-
-// ---------------------------------------------------------------------------
-// Common device helpers
-
-// Reflect-101 border: ... c b | a b c ... (index -1 -> 1), repeated with
-// period 2(n-1) for indices far outside; n == 1 maps everything to 0.
-__device__ __forceinline__ int mirror(int i, int n) {
-  if (i >= 0 && i < n) return i;
-  if (n == 1) return 0;
-  const int period = 2 * (n - 1);
-  i = i < 0 ? -i : i;
-  i %= period;
-  return i >= n ? period - i : i;
-}
-
-// Largest idx in [0, n) with prefix[idx] <= item (prefix has n + 1 entries).
-__device__ __forceinline__ int find_owner(const int* prefix, int n, int item) {
-  int lo = 0, hi = n;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (prefix[mid] <= item) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
-__device__ __forceinline__ int* counters_of(char* ws, const ImgEntry& e) {
-  return reinterpret_cast<int*>(ws + e.region);
-}
-
-__device__ __forceinline__ const float* level_ptr(char* ws, const ImgEntry& e, const OctView& ov,
-                                                  int level) {
-  return reinterpret_cast<const float*>(ws + e.region + ov.level0 + (int64_t)level * ov.plane);
-}
-
-// Inclusive sum of an int over the 64 lanes of a wave (exact, any order).
-__device__ __forceinline__ int wave_incl_scan(int v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
-  }
-  return v;
-}
-
-// Butterfly sum over the 64 lanes.  Each step adds the partner's value; the
-// two partners add the same two operands, so every lane ends with the same
-// bits and the association order is fixed by the code.
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v = v + __shfl_xor(v, d, 64);
-  return v;
-}
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
-  return v;
-}
-
-// Add v into a lane-private LDS cell.  No other lane ever touches the cell,
-// so the adds into it happen in program order: the result is the same
-// sequential sum on every run.  The add is fire-and-forget (no value comes
-// back), so a lane issues its updates without waiting on LDS latency.
-__device__ __forceinline__ void lds_add_private(float* cell, float v) {
-  __hip_atomic_fetch_add(cell, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-}
-
-// Make this wave's LDS writes visible to its other lanes before they read.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Block-wide exclusive scan of ints (blockDim.x == 256).  Returns the
-// exclusive prefix of v; *total receives the block sum.
-__device__ __forceinline__ int block_excl_scan256(int v, int* s_wave, int* total) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int incl = wave_incl_scan(v);
-  if (lane == 63) s_wave[wave] = incl;
-  __syncthreads();
-  int base = 0, sum = 0;
-#pragma unroll
-  for (int wv = 0; wv < 4; ++wv) {
-    const int t = s_wave[wv];
-    if (wv < wave) base += t;
-    sum += t;
-  }
-  __syncthreads();
-  *total = sum;
-  return base + incl - v;
-}
 
 // ---------------------------------------------------------------------------
 // Setup: copy image-table entries from kernel arguments into the workspace,
@@ -145,268 +51,6 @@ __global__ void k_finalize(HdrPtrs hp, int n, DevParams p) {
       acc += region_tail(tab[i].h, tab[i].w, lc).total_bands;
       bp[i + 1] = acc;
     }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Gaussian level: separable blur, one work-group per strip of kTileW columns
-// and up to `th` rows of one image.  The group walks down its strip in steps
-// of B = kBlurRows rows: it stages B source rows (plus an R-column mirrored
-// halo) in LDS, runs the horizontal pass over them into a ring of horizontally
-// blurred rows, and runs the vertical pass over the ring to emit B output
-// rows.  Each source row is staged once per strip and each horizontal result
-// computed once, so apart from the 2R-row lead-in at the top of a chunk there
-// is no halo recomputation.  Source rows of the next step are fetched into
-// registers while the current step computes.
-//
-// Each output is
-//   acc = 0; for t = 0..2R: acc = fma(g[t], in[x - R + t], acc)
-// for the horizontal pass and the same along columns for the vertical pass,
-// whatever the strip or chunk shape.  Levels are held relative to mid-grey
-// (L - 0.5): the blur is linear with unit-sum taps, so this changes no
-// difference of levels and keeps fp32 rounding error proportional to |L - 0.5|.
-//
-// Work-groups are dealt round-robin to the 8 XCDs, each with its own L2; the
-// grid is a multiple of 8 and group b takes work item (b % 8) * (grid / 8) +
-// b / 8, so every XCD sweeps one contiguous run of items and neighbouring
-// strips find their shared halo columns in the same L2.
-
-// LDS row stride of at least n floats with stride % 8 == 4: lanes that read
-// 16 bytes each from 8 consecutive rows then touch 8 distinct bank groups.
-constexpr int lds_stride4(int n) {
-  return ((n + 3) / 4 * 4) % 8 == 4 ? (n + 3) / 4 * 4 : (n + 3) / 4 * 4 + 4;
-}
-
-// Pointers into device memory that the compiler must treat as global (a
-// pointer read from the image table would otherwise be accessed as flat,
-// whose completion the LDS wait counter also tracks).
-typedef __attribute__((address_space(1))) float gfloat;
-typedef __attribute__((address_space(1))) char gchar;
-__device__ __forceinline__ gfloat* as_global(const float* p) { return (gfloat*)(p); }
-
-// A pointer every lane holds the same value of, moved to scalar registers so
-// that loads and stores use the scalar-base + 32-bit vector-offset form.
-__device__ __forceinline__ gchar* uniform_ptr(const gchar* p) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
-  return reinterpret_cast<gchar*>((static_cast<uint64_t>(hi) << 32) | lo);
-}
-__device__ __forceinline__ float load_at(const gchar* row, uint32_t byte_off) {
-  return *reinterpret_cast<const gfloat*>(row + byte_off);
-}
-__device__ __forceinline__ void store_at(gchar* row, uint32_t byte_off, float v) {
-  *reinterpret_cast<gfloat*>(row + byte_off) = v;
-}
-
-// UP selects the source of level 0 of the upsampled octave (bilinear 2x of
-// the input image); otherwise a source pixel is src[y * sp + x * sx] - bias.
-template <int R, bool UP>
-__global__ __launch_bounds__(kTileW) void k_blur(BlurArgs a) {
-  constexpr int TW = kTileW;          // output columns; one thread per column
-  constexpr int B = kBlurRows;        // rows per step
-  constexpr int HB = 16;              // horizontal outputs per thread
-  constexpr int WI = TW + 2 * R;      // staged source columns
-  constexpr int SS = lds_stride4(WI);
-  constexpr int RS = lds_stride4(TW);
-  constexpr int NB = (2 * R + B - 1) / B + 1;   // ring blocks of B rows
-  constexpr int NH = (2 * R + HB + 3) / 4;      // float4 reads per horizontal task
-  static_assert((TW / HB) * B == TW, "one horizontal task per thread");
-  static_assert(TW + 2 * R <= 2 * TW, "two staged columns per thread");
-  __shared__ __align__(16) float s_in[B * SS];
-  __shared__ __align__(16) float s_ring[NB * B * RS];
-
-  const int* tp = a.tile_prefix;
-  const int per_xcd = gridDim.x / kXcds;
-  const int item = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
-  if (item >= tp[a.n]) return;
-  const int img = find_owner(tp, a.n, item);
-  const int local = item - tp[img];
-  const ImgEntry e = a.table[img];
-  const LayoutCfg lc = layout_cfg(a.p);
-  const int k = a.k;
-  const OctView ov = octave_view(e.h, e.w, lc, k);
-  const int hk = ov.h, wk = ov.w, pk = ov.pitch;
-  const int strips = cdiv(wk, TW);
-  const int cy = local / strips;
-  const int sx = local - cy * strips;
-  const int x0 = sx * TW, y0 = cy * a.th;
-  const int y1 = min(y0 + a.th, hk);
-  gchar* gdst = reinterpret_cast<gchar*>(as_global(level_ptr(a.ws, e, ov, a.dst_level)));
-  const int t = threadIdx.x;
-  const int mode = a.mode;
-
-  // ---- per-thread source columns (staged columns t and t + TW)
-  const bool has1 = t + TW < WI;
-  const int xc0 = mirror(x0 - R + t, wk);
-  const int xc1 = has1 ? mirror(x0 - R + t + TW, wk) : xc0;
-  const float* src;
-  int64_t sp;          // source row pitch in bytes
-  int csh;             // source column = staged column << csh
-  float bias = 0.0f;
-  if (UP || mode == kSrcImage) {
-    src = e.src;
-    sp = 4 * (int64_t)e.src_pitch;
-    csh = 0;
-    bias = kCentre;
-  } else if (mode == kSrcLevel) {
-    src = level_ptr(a.ws, e, ov, a.dst_level - 1);
-    sp = 4 * (int64_t)pk;
-    csh = 0;
-  } else {
-    // level s of the previous octave at every second row and column
-    const OctView pv = octave_view(e.h, e.w, lc, k - 1);
-    src = level_ptr(a.ws, e, pv, a.p.s);
-    sp = 8 * (int64_t)pv.pitch;
-    csh = 1;
-  }
-  const gchar* gsrc = uniform_ptr(reinterpret_cast<const gchar*>(as_global(src)));
-  const uint32_t bo0 = (uint32_t)(xc0 << csh) * 4u, bo1 = (uint32_t)(xc1 << csh) * 4u;
-  // bilinear 2x upsampling: U[y][x] = I(y/2, x/2), the sample past the last
-  // row or column clamped to it; computed on centred values
-  const uint32_t ua0 = (uint32_t)(xc0 >> 1) * 4u, ub0 = (uint32_t)min((xc0 >> 1) + 1, e.w - 1) * 4u;
-  const uint32_t ua1 = (uint32_t)(xc1 >> 1) * 4u, ub1 = (uint32_t)min((xc1 >> 1) + 1, e.w - 1) * 4u;
-  const bool uo0 = xc0 & 1, uo1 = xc1 & 1;
-
-  // H-row h (h = 0 is image row y0 - R) belongs to block h / B
-  const int M = cdiv(y1 - y0, B);     // output steps
-  const int NBLK = M + NB - 1;        // horizontal blocks
-  float v0[B], v1[B];
-  // Loads are issued unconditionally (lanes without a second column reload
-  // their first) and blended afterwards, so no load sits under a branch that
-  // would force an early wait for it.
-  auto fetch_row = [&](int y, int r) {
-    if (UP) {
-      const int ya = y >> 1, yb = min(ya + 1, e.h - 1);
-      const gchar* r0 = uniform_ptr(gsrc + ya * sp);
-      const gchar* r1 = uniform_ptr(gsrc + ((y & 1) ? yb : ya) * sp);
-      const float a0 = load_at(r0, ua0), b0 = load_at(r0, ub0);
-      const float c0 = load_at(r1, ua0), d0 = load_at(r1, ub0);
-      const float a1 = load_at(r0, ua1), b1 = load_at(r0, ub1);
-      const float c1 = load_at(r1, ua1), d1 = load_at(r1, ub1);
-      float top0 = a0 - bias, bot0 = c0 - bias, top1 = a1 - bias, bot1 = c1 - bias;
-      top0 = uo0 ? (top0 + (b0 - bias)) * 0.5f : top0;
-      bot0 = uo0 ? (bot0 + (d0 - bias)) * 0.5f : bot0;
-      top1 = uo1 ? (top1 + (b1 - bias)) * 0.5f : top1;
-      bot1 = uo1 ? (bot1 + (d1 - bias)) * 0.5f : bot1;
-      v0[r] = (y & 1) ? (top0 + bot0) * 0.5f : top0;
-      v1[r] = (y & 1) ? (top1 + bot1) * 0.5f : top1;
-    } else {
-      const gchar* row = uniform_ptr(gsrc + y * sp);
-      v0[r] = load_at(row, bo0) - bias;
-      v1[r] = load_at(row, bo1) - bias;
-    }
-  };
-  auto load_block = [&](int beta) {
-    const int ybase = y0 - R + beta * B;
-    if (ybase >= 0 && ybase + B <= hk) {
-#pragma unroll
-      for (int r = 0; r < B; ++r) fetch_row(ybase + r, r);
-    } else {
-#pragma unroll
-      for (int r = 0; r < B; ++r) fetch_row(mirror(ybase + r, hk), r);
-    }
-  };
-  gchar* l0 = nullptr;
-  if (!UP && mode == kSrcDown)
-    l0 = uniform_ptr(reinterpret_cast<gchar*>(as_global(level_ptr(a.ws, e, ov, 0))));
-  const int xend = min(x0 + TW, wk);
-  const int64_t pkb = 4 * (int64_t)pk;
-  auto store_block = [&](int beta) {
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-      s_in[r * SS + t] = v0[r];
-      if (has1) s_in[r * SS + t + TW] = v1[r];
-    }
-    if (!UP && mode == kSrcDown) {
-      // the subsampled base is this octave's level 0: written by the chunk
-      // that owns the row and the strip that owns the column
-      const int xa = x0 - R + t, xb = xa + TW;
-      for (int r = 0; r < B; ++r) {
-        const int y = y0 - R + beta * B + r;
-        if (y >= y0 && y < y1) {
-          gchar* row = uniform_ptr(l0 + y * pkb);
-          if (xa >= x0 && xa < xend) store_at(row, (uint32_t)xa * 4u, v0[r]);
-          if (has1 && xb < xend) store_at(row, (uint32_t)xb * 4u, v1[r]);
-        }
-      }
-    }
-  };
-
-  // horizontal pass of the staged block into ring slot `slot`
-  const int hr = t % B, hq = t / B;
-  auto hpass = [&](int slot) {
-    const float4* in = reinterpret_cast<const float4*>(&s_in[hr * SS + hq * HB]);
-    float acc[HB];
-#pragma unroll
-    for (int m = 0; m < HB; ++m) acc[m] = 0.0f;
-#pragma unroll
-    for (int j4 = 0; j4 < NH; ++j4) {
-      const float4 q = in[j4];
-      const float qv[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = 4 * j4 + u;
-#pragma unroll
-        for (int m = 0; m < HB; ++m) {
-          const int tt = j - m;
-          if (tt >= 0 && tt <= 2 * R) acc[m] = __fmaf_rn(a.taps[tt], qv[u], acc[m]);
-        }
-      }
-    }
-    float4* out = reinterpret_cast<float4*>(&s_ring[(slot * B + hr) * RS + hq * HB]);
-#pragma unroll
-    for (int m = 0; m < HB / 4; ++m)
-      out[m] = make_float4(acc[4 * m], acc[4 * m + 1], acc[4 * m + 2], acc[4 * m + 3]);
-  };
-
-  // vertical pass: output rows y0 + mB .. + B - 1 at column x0 + t; H-row
-  // mB + j lives in block m + j / B, i.e. ring slot (m + j / B) % NB
-  const bool col_ok = x0 + t < wk;
-  auto vpass = [&](int m) {
-    const float* base[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) base[q] = &s_ring[((m + q) % NB) * B * RS + t];
-    float acc[B];
-#pragma unroll
-    for (int i = 0; i < B; ++i) acc[i] = 0.0f;
-#pragma unroll
-    for (int j = 0; j < B + 2 * R; ++j) {
-      const float v = base[j / B][(j % B) * RS];
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const int tt = j - i;
-        if (tt >= 0 && tt <= 2 * R) acc[i] = __fmaf_rn(a.taps[tt], v, acc[i]);
-      }
-    }
-    if (col_ok) {
-      const int yb = y0 + m * B;
-      const uint32_t off = (uint32_t)(x0 + t) * 4u;
-#pragma unroll
-      for (int i = 0; i < B; ++i)
-        if (yb + i < y1) store_at(uniform_ptr(gdst + (yb + i) * pkb), off, acc[i]);
-    }
-  };
-
-  // lead-in: blocks 0 .. NB - 2 hold H-rows y0 - R .. y0 - R + (NB - 1) B - 1
-  load_block(0);
-  for (int beta = 0; beta < NB - 1; ++beta) {
-    if (beta > 0) __syncthreads();     // previous horizontal pass done with s_in
-    store_block(beta);
-    __syncthreads();
-    load_block(beta + 1);              // NBLK >= NB, so block beta + 1 exists
-    hpass(beta);
-  }
-  // step m: block m + NB - 1 into slot (m + NB - 1) % NB, then outputs of step m
-  for (int m = 0; m < M; ++m) {
-    const int beta = m + NB - 1;
-    __syncthreads();                   // s_in free; ring slot of block m - 1 free
-    store_block(beta);
-    __syncthreads();
-    if (beta + 1 < NBLK) load_block(beta + 1);
-    hpass(beta % NB);
-    __syncthreads();
-    vpass(m);
   }
 }
 
@@ -729,7 +373,9 @@ __global__ __launch_bounds__(256) void k_refine(char* ws, HdrPtrs hp, int n, Dev
 // are dealt to lanes in a fixed order; each lane accumulates into its own
 // LDS column of the 36-bin histogram (layout [bin][lane]: no two lanes share
 // an address, so each column is a sequential sum), a sample's weight split
-// linearly between the two nearest bins.  Bins are then summed over lanes in a fixed order, smoothed
+// linearly between the two nearest bins.  Gradient orientations come from
+// a polynomial arctangent (error 1.4e-7 rad), weights from the hardware
+// exponential.  Bins are then summed over lanes in a fixed order, smoothed
 // once with [1/4, 1/2, 1/4], and every strict local maximum >= peak_ratio *
 // max gives an orientation refined by a parabola through the bin and its two
 // neighbours.
@@ -801,10 +447,10 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
         if (!ok[u]) continue;
         const float gx = ga[u] - gb[u];
         const float gy = gc[u] - gd[u];
-        const float mag = sqrtf(gx * gx + gy * gy);
-        float th = atan2f(gy, gx);
+        const float mag = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);
+        float th = atan2_poly(gy, gx);
         if (th < 0.0f) th += kTwoPi;
-        const float wgt = expf(-(float)(ddx[u] * ddx[u] + ddy[u] * ddy[u]) * inv2) * mag;
+        const float wgt = exp_fast(-(float)(ddx[u] * ddx[u] + ddy[u] * ddy[u]) * inv2) * mag;
         const float pos = th * ((float)kOriBins / kTwoPi);
         const float fl = floorf(pos);
         const float f = pos - fl;
@@ -812,8 +458,12 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
         if (b0 >= kOriBins) b0 -= kOriBins;
         int b1 = b0 + 1;
         if (b1 >= kOriBins) b1 -= kOriBins;
-        lds_add_private(&hist[b0 * 64 + lane], wgt * (1.0f - f));
-        lds_add_private(&hist[b1 * 64 + lane], wgt * f);
+        // the two bins differ: read both, then write both
+        float* c0 = &hist[b0 * 64 + lane];
+        float* c1 = &hist[b1 * 64 + lane];
+        const float h0 = *c0, h1 = *c1;
+        *c0 = h0 + wgt * (1.0f - f);
+        *c1 = h1 + wgt * f;
       }
     }
     wave_lds_sync();
@@ -885,11 +535,15 @@ __global__ __launch_bounds__(256) void k_ori_scan(char* ws, HdrPtrs hp, int n, D
 
 // ---------------------------------------------------------------------------
 // Descriptor: one wave per output keypoint.  For each pooled domain size the
-// window of the rotated 4x4 grid is swept with samples dealt to lanes in a
-// fixed order; each lane accumulates trilinear contributions into its own LDS
-// column of the 128-bin histogram.  The lane columns are summed in a fixed
-// order, averaged over domain sizes, then L2-normalised, clamped, L2-normalised
-// and optionally turned into RootSIFT (L1 normalise, square root).
+// bounding square of the rotated 4x4 grid is scanned 64 samples at a time;
+// the samples whose rotated cell coordinates fall in (-1, 4) (about 60% of
+// the square) are packed, with their pixel gradients, into full 64-lane
+// batches by a lane permutation in registers, so the trilinear binning runs
+// with every lane busy.  Each lane accumulates into its own LDS column of the
+// 128-bin histogram.  Scan, packing and column order are fixed, so the sums
+// are too.  The lane columns are summed in a fixed order, averaged over domain
+// sizes, then L2-normalised, clamped, L2-normalised and optionally turned into
+// RootSIFT (L1 normalise, square root).
 
 __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, DevParams p) {
   __shared__ float hist[kDescDim * 64];
@@ -937,24 +591,86 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
       const int R = (int)ceilf(2.5f * wc * (fabsf(ct) + fabsf(st))) + 1;
       const int side = 2 * R + 1;
       const int nsamp = side * side;
-      // U samples per lane per pass: their loads are all issued before any is used
-      constexpr int U = 4;
-      for (int q0 = lane; q0 < nsamp; q0 += 64 * U) {
-        float ga[U], gb[U], gc[U], gd[U], xr[U], yr[U];
+
+      // rotated, cell-scaled coordinates of offset (dx, dy)
+      auto rotate = [&](int dx, int dy, float& xr, float& yr) {
+        const float fu = (float)dx - kp.dx;
+        const float fv = (float)dy - kp.dy;
+        xr = (ct * fu + st * fv) * inv_wc;
+        yr = (ct * fv - st * fu) * inv_wc;
+      };
+      // trilinear binning of one contributing sample into this lane's column
+      auto accumulate = [&](int pxy, float gx, float gy) {
+        const int dx = (int)(short)(pxy & 0xffff), dy = pxy >> 16;
+        float xr, yr;
+        rotate(dx, dy, xr, yr);
+        const float rb = yr + 1.5f, cb = xr + 1.5f;
+        const float mag = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);
+        float ta = atan2_poly(gy, gx);
+        if (ta < 0.0f) ta += kTwoPi;
+        float ob = ta - th;
+        if (ob < 0.0f) ob += kTwoPi;
+        if (ob >= kTwoPi) ob -= kTwoPi;
+        ob = ob * (8.0f / kTwoPi);
+        const float wgt = mag * exp_fast(-(xr * xr + yr * yr) * 0.125f);
+        const float r0 = floorf(rb), c0 = floorf(cb), o0 = floorf(ob);
+        const float fr = rb - r0, fc = cb - c0, fo = ob - o0;
+        const int ir = (int)r0, ic = (int)c0;
+        int io = (int)o0;
+        if (io >= 8) io -= 8;
+        // The 2 x 2 cells around (rb, cb), orientations io and io + 1.  A
+        // cell outside the 4 x 4 grid adds +0 to orientations io + 4 and
+        // io + 5 of the nearest grid cell: those are never among the other
+        // targets, and adding +0 to a non-negative sum leaves it unchanged.
+        // The eight targets of one sample are thus read first, then written.
+        float wv[8];
+        int bv[8];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int row_b = ir + a;
+          const float wr = a ? fr : 1.0f - fr;
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb) {
+            const int col_b = ic + bb;
+            const bool in = row_b >= 0 && row_b <= 3 && col_b >= 0 && col_b <= 3;
+            const int cell = (min(max(row_b, 0), 3) * 4 + min(max(col_b, 0), 3)) * 8;
+            const int oa = in ? io : (io + 4) & 7;
+            const float w2 = wgt * wr * (bb ? fc : 1.0f - fc);
+            wv[4 * a + 2 * bb] = in ? w2 * (1.0f - fo) : 0.0f;
+            wv[4 * a + 2 * bb + 1] = in ? w2 * fo : 0.0f;
+            bv[4 * a + 2 * bb] = (cell + oa) * 64 + lane;
+            bv[4 * a + 2 * bb + 1] = (cell + ((oa + 1) & 7)) * 64 + lane;
+          }
+        }
+        float hv[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) hv[c] = hist[bv[c]];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) hist[bv[c]] = hv[c] + wv[c];
+      };
+
+      // Pending contributing samples sit in lanes [0, fill): packed offset
+      // (dy << 16 | dx & 0xffff) and gradient.
+      int fill = 0;
+      int p_xy = 0;
+      float p_gx = 0.0f, p_gy = 0.0f;
+      constexpr int U = 4;   // scan batches whose loads are issued together
+      for (int q0 = 0; q0 < nsamp; q0 += 64 * U) {
+        float ga[U], gb[U], gc[U], gd[U];
+        int sxy[U];
         bool ok[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int qq = q0 + 64 * u;
+          const int qq = q0 + 64 * u + lane;
           const int qy = qq / side;
           const int dy = qy - R, dx = qq - qy * side - R;
           const int rr = kp.r + dy, cc = kp.c + dx;
-          const float fu = (float)dx - kp.dx;
-          const float fv = (float)dy - kp.dy;
-          xr[u] = (ct * fu + st * fv) * inv_wc;
-          yr[u] = (ct * fv - st * fu) * inv_wc;
-          const float rb = yr[u] + 1.5f, cb = xr[u] + 1.5f;
+          float xr, yr;
+          rotate(dx, dy, xr, yr);
+          const float rb = yr + 1.5f, cb = xr + 1.5f;
           ok[u] = qq < nsamp && rr >= 1 && rr <= hk - 2 && cc >= 1 && cc <= wk - 2 &&
                   rb > -1.0f && rb < 4.0f && cb > -1.0f && cb < 4.0f;
+          sxy[u] = (dy << 16) | (dx & 0xffff);
           // samples that do not contribute read the (interior) centre instead
           const float* row = L + (int64_t)(ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c);
           ga[u] = row[1];
@@ -964,42 +680,33 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          if (!ok[u]) continue;
-          const float gx = ga[u] - gb[u];
-          const float gy = gc[u] - gd[u];
-          const float rb = yr[u] + 1.5f, cb = xr[u] + 1.5f;
-          const float mag = sqrtf(gx * gx + gy * gy);
-          float ta = atan2f(gy, gx);
-          if (ta < 0.0f) ta += kTwoPi;
-          float ob = ta - th;
-          if (ob < 0.0f) ob += kTwoPi;
-          if (ob >= kTwoPi) ob -= kTwoPi;
-          ob = ob * (8.0f / kTwoPi);
-          const float wgt = mag * expf(-(xr[u] * xr[u] + yr[u] * yr[u]) * 0.125f);
-          const float r0 = floorf(rb), c0 = floorf(cb), o0 = floorf(ob);
-          const float fr = rb - r0, fc = cb - c0, fo = ob - o0;
-          const int ir = (int)r0, ic = (int)c0;
-          int io = (int)o0;
-          if (io >= 8) io -= 8;
-          const int io1 = (io + 1) & 7;
-#pragma unroll
-          for (int a = 0; a < 2; ++a) {
-            const int row_b = ir + a;
-            if (row_b < 0 || row_b > 3) continue;
-            const float wr = a ? fr : 1.0f - fr;
-#pragma unroll
-            for (int bb = 0; bb < 2; ++bb) {
-              const int col_b = ic + bb;
-              if (col_b < 0 || col_b > 3) continue;
-              const float wcl = bb ? fc : 1.0f - fc;
-              const float w2 = wgt * wr * wcl;
-              const int cell = (row_b * 4 + col_b) * 8;
-              lds_add_private(&hist[(cell + io) * 64 + lane], w2 * (1.0f - fo));
-              lds_add_private(&hist[(cell + io1) * 64 + lane], w2 * fo);
-            }
+          const uint64_t m = __ballot(ok[u]);
+          const int cnt = __popcll(m);
+          const int rank = __popcll(m & lanemask_lt());
+          // contributing lanes go to [fill, fill + cnt), the others after them
+          const int dest = (ok[u] ? fill + rank : fill + cnt + (lane - rank)) & 63;
+          const int r_xy = lane_send(dest, sxy[u]);
+          const float r_gx = lane_send(dest, ga[u] - gb[u]);
+          const float r_gy = lane_send(dest, gc[u] - gd[u]);
+          const int nf = fill + cnt;
+          if (nf >= 64) {
+            // lanes [fill, 64) complete the batch; lanes [0, nf - 64) overflow
+            const bool fresh = lane >= fill;
+            accumulate(fresh ? r_xy : p_xy, fresh ? r_gx : p_gx, fresh ? r_gy : p_gy);
+            p_xy = r_xy;
+            p_gx = r_gx;
+            p_gy = r_gy;
+            fill = nf - 64;
+          } else {
+            const bool take = lane >= fill && lane < nf;
+            p_xy = take ? r_xy : p_xy;
+            p_gx = take ? r_gx : p_gx;
+            p_gy = take ? r_gy : p_gy;
+            fill = nf;
           }
         }
       }
+      if (lane < fill) accumulate(p_xy, p_gx, p_gy);
     }
     wave_lds_sync();
     float h0 = 0.0f, h1 = 0.0f;
@@ -1048,15 +755,7 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
 }
 
 // ---------------------------------------------------------------------------
-// Launch helpers: hipLaunchKernel returns the launch status directly (the
-// thread's last-error slot may hold another library's stale error).
-
-template <typename... Args>
-static hipError_t launch(void (*kernel)(Args...), dim3 grid, dim3 block, hipStream_t stream,
-                         Args... args) {
-  void* ptrs[] = {static_cast<void*>(&args)...};
-  return hipLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, ptrs, 0, stream);
-}
+// Launch helpers
 
 hipError_t launch_setup(const HdrPtrs& hp, const SetupChunk& c, hipStream_t stream) {
   return launch(k_setup, dim3(1), dim3(64), stream, hp, c);
@@ -1064,30 +763,6 @@ hipError_t launch_setup(const HdrPtrs& hp, const SetupChunk& c, hipStream_t stre
 
 hipError_t launch_finalize(const HdrPtrs& hp, int n, const DevParams& p, hipStream_t stream) {
   return launch(k_finalize, dim3(1), dim3(64), stream, hp, n, p);
-}
-
-typedef void (*BlurKernel)(BlurArgs);
-
-#define SIFT_BLUR_CASE(RR) \
-  case RR: return up ? k_blur<RR, true> : k_blur<RR, false>;
-
-static BlurKernel blur_kernel(int radius, bool up) {
-  switch (radius) {
-    SIFT_BLUR_CASE(1) SIFT_BLUR_CASE(2) SIFT_BLUR_CASE(3) SIFT_BLUR_CASE(4)
-    SIFT_BLUR_CASE(5) SIFT_BLUR_CASE(6) SIFT_BLUR_CASE(7) SIFT_BLUR_CASE(8)
-    SIFT_BLUR_CASE(9) SIFT_BLUR_CASE(10) SIFT_BLUR_CASE(11) SIFT_BLUR_CASE(12)
-    SIFT_BLUR_CASE(13) SIFT_BLUR_CASE(14) SIFT_BLUR_CASE(15) SIFT_BLUR_CASE(16)
-    SIFT_BLUR_CASE(17) SIFT_BLUR_CASE(18) SIFT_BLUR_CASE(19) SIFT_BLUR_CASE(20)
-    SIFT_BLUR_CASE(21) SIFT_BLUR_CASE(22) SIFT_BLUR_CASE(23) SIFT_BLUR_CASE(24)
-    default: return nullptr;
-  }
-}
-#undef SIFT_BLUR_CASE
-
-hipError_t launch_blur(const BlurArgs& a, int radius, int grid, hipStream_t stream) {
-  BlurKernel fn = blur_kernel(radius, a.mode == kSrcUpsample);
-  if (!fn || a.th % kBlurRows != 0) return hipErrorInvalidValue;
-  return launch(fn, dim3(grid), dim3(kTileW), stream, a);
 }
 
 hipError_t launch_detect(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
