@@ -27,22 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_2605_17869_amd import synth  # noqa: E402
+from paper_2605_17869_amd.build import kernel_source_hash  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# sources of the blur kernel: a traffic figure holds only while they are unchanged
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2605_17869_amd", "csrc", f)
-                  for f in ("sift_blur.hip", "sift_device.h", "sift_internal.h")]
+# HBM traffic of the blur kernel measured with rocprofv3 counters (summary text)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blur_hbm_traffic_w2.txt")
-
-
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
-        with open(path, "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def measured_traffic():
     """HBM bytes per blur launch from the committed counter summary, or None
     when it is missing or was taken on a different kernel source."""

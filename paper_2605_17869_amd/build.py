@@ -59,20 +59,28 @@ def smem_misaligned(asm_text: str) -> list:
     return bad
 
 
-def device_asm(src: Path, out: Path) -> str:
-    cmd = [hipcc(), "-x", "hip", *HIP_FLAGS, "--offload-device-only", "-S", str(src), "-o", str(out)]
-    subprocess.run(cmd, check=True, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
-    return out.read_text()
+def device_asm_cmd(src: Path, out: Path) -> list:
+    return [hipcc(), "-x", "hip", *HIP_FLAGS, "--offload-device-only", "-S", str(src), "-o", str(out)]
 
 
-def check_smem(sources, out_dir: Path):
+def check_smem(asm_files):
     """Fail the build if any kernel has a misaligned scalar-memory immediate."""
     problems = []
-    for src in sources:
-        problems += smem_misaligned(device_asm(src, out_dir / (src.name + ".s")))
+    for path in asm_files:
+        problems += smem_misaligned(Path(path).read_text())
     if problems:
         lines = "\n".join(f"  {fn}: {ins}" for fn, ins in problems[:20])
         raise RuntimeError(f"scalar memory access with a misaligned immediate offset:\n{lines}")
+
+
+def kernel_source_hash(names=("sift_blur.hip", "sift_device.h", "sift_internal.h")) -> str:
+    """Short digest of kernel sources (default: those the blur kernel is built
+    from); measured figures recorded for a kernel name the digest they hold for."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in names:
+        h.update((CSRC / name).read_bytes())
+    return h.hexdigest()[:16]
 
 
 def build_library(verbose: bool = False) -> Path:
@@ -82,14 +90,19 @@ def build_library(verbose: bool = False) -> Path:
     out_dir.mkdir(exist_ok=True)
     sources = sorted(CSRC.glob("*.hip")) + sorted(CSRC.glob("*.cpp"))
     procs = []
+    asm_files = []
     for src in sources:
         obj = out_dir / (src.name + ".o")
-        lang = ["-x", "hip"]
-        cmd = [hipcc(), *lang, *HIP_FLAGS, "-c", str(src), "-o", str(obj)]
+        cmd = [hipcc(), "-x", "hip", *HIP_FLAGS, "-c", str(src), "-o", str(obj)]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         objs.append(obj)
+        if src.suffix == ".hip":
+            asm = out_dir / (src.name + ".s")
+            procs.append((src, subprocess.Popen(device_asm_cmd(src, asm), stdout=subprocess.PIPE,
+                                                stderr=subprocess.STDOUT)))
+            asm_files.append(asm)
     failed = []
     for src, pr in procs:
         out, _ = pr.communicate()
@@ -100,7 +113,7 @@ def build_library(verbose: bool = False) -> Path:
     if failed:
         msg = "\n".join(f"--- {s}\n{o}" for s, o in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
-    check_smem([src for src in sources if src.suffix == ".hip"], out_dir)
+    check_smem(asm_files)
     tmp = LIB.with_suffix(".so.tmp")
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), *map(str, objs)]
     if verbose:

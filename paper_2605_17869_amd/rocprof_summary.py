@@ -3,12 +3,19 @@
     python -m paper_2605_17869_amd.rocprof_summary trace DB [--group PREFIX ...]
     python -m paper_2605_17869_amd.rocprof_summary counters DB COUNTER [--group PREFIX ...]
     python -m paper_2605_17869_amd.rocprof_summary calibrate DB COUNTER KERNEL BYTES_PER_DISPATCH
+    python -m paper_2605_17869_amd.rocprof_summary traffic FETCH_DB WRITE_DB CAL_FETCH_DB \
+        CAL_WRITE_DB CAL_KERNEL CAL_BYTES PREFIX
 
 ``trace`` prints per-kernel calls, total and average duration (from a
 ``--kernel-trace`` run); ``counters`` prints the per-dispatch average of one
 counter per kernel (from a ``--pmc`` run); ``calibrate`` prints the ratio of a
 known per-dispatch byte count to what the counter reports for a plain copy
-kernel.  ``--group`` sums kernels whose demangled name starts with PREFIX.
+kernel.  ``traffic`` turns FETCH_SIZE and WRITE_SIZE of the kernels whose
+name starts with PREFIX into HBM bytes per launch, each counter scaled by
+CAL_BYTES over what it reports per dispatch of the calibration kernel (the
+first kernel whose name contains CAL_KERNEL), and prints the digest of the
+blur kernel's sources the figure holds for.  ``--group`` sums kernels whose
+demangled name starts with PREFIX.
 """
 from __future__ import annotations
 
@@ -48,7 +55,7 @@ def grouped(items: "OrderedDict", groups) -> "OrderedDict":
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "counters", "calibrate"])
+    ap.add_argument("mode", choices=["trace", "counters", "calibrate", "traffic"])
     ap.add_argument("db")
     ap.add_argument("rest", nargs="*")
     ap.add_argument("--group", action="append", default=[])
@@ -72,6 +79,25 @@ def main(argv=None):
         print(f"{'kernel':60s} {'dispatches':>10s} {counter + '_KiB_per_dispatch':>28s}")
         for k, (n, s) in v.items():
             print(f"{k[:60]:60s} {n:10d} {s / n:28.1f}")
+    elif a.mode == "traffic":
+        fetch_db, write_db, cal_fetch, cal_write, cal_kernel = a.db, *a.rest[:4]
+        cal_bytes, prefix = float(a.rest[4]), a.rest[5]
+        out = {}
+        for counter, db, cal in (("FETCH_SIZE", fetch_db, cal_fetch), ("WRITE_SIZE", write_db, cal_write)):
+            cv = counter_values(cal, counter)
+            name = next(k for k in cv if cal_kernel in k)
+            cn, cs = cv[name]
+            scale = cal_bytes / (cs / cn * 1024.0)
+            kv = [(n, s_) for k, (n, s_) in counter_values(db, counter).items() if k.startswith(prefix)]
+            launches = sum(n for n, _ in kv)
+            raw = sum(s_ for _, s_ in kv) / launches * 1024.0
+            out[counter] = raw * scale
+            print(f"{counter}: {raw:.0f} bytes/launch reported over {launches} launches of {prefix}*; "
+                  f"calibration {name[:40]}: {cs / cn * 1024.0:.0f} reported for {cal_bytes:.0f}, "
+                  f"scale {scale:.4f}; scaled {raw * scale:.0f} bytes/launch")
+        from paper_2605_17869_amd.build import kernel_source_hash
+        print(f"hbm_bytes_per_launch: {int(round(out['FETCH_SIZE'] + out['WRITE_SIZE']))}")
+        print(f"kernel_source_sha256: {kernel_source_hash()}")
     else:
         counter, kernel, expected = a.rest[0], a.rest[1], float(a.rest[2])
         v = counter_values(a.db, counter)

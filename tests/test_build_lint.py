@@ -2,6 +2,8 @@
 immediate offset (the scalar unit ignores the low bits of the base register,
 so such an access would read the wrong dword).  CPU only: compiles to gfx950
 assembly and inspects it."""
+import subprocess
+
 from paper_2605_17869_amd import build
 
 
@@ -11,7 +13,12 @@ def test_lint_flags_a_misaligned_immediate():
 
 
 def test_kernels_have_no_misaligned_scalar_offsets(tmp_path):
+    jobs = []
     for src in sorted(build.CSRC.glob("*.hip")):
-        text = build.device_asm(src, tmp_path / (src.name + ".s"))
+        out = tmp_path / (src.name + ".s")
+        jobs.append((out, subprocess.Popen(build.device_asm_cmd(src, out))))
+    for out, pr in jobs:
+        assert pr.wait() == 0
+        text = out.read_text()
         assert "s_load" in text
         assert build.smem_misaligned(text) == []
