@@ -83,6 +83,79 @@ def digest(kp, desc) -> str:
     return h.hexdigest()
 
 
+def serve_bench(args):
+    """Serving: requests arrive as a Poisson process at fractions of the
+    batched saturation rate; the continuous-batching server and the plain
+    one-at-a-time path (max_batch 1, one in flight) serve the same arrivals.
+    Latency is submit to observed completion, measured by the server."""
+    import torch
+    import paper_2605_17869_amd as sm
+    wl = synth.workload(4, args.unique_images)
+    t0 = time.time()
+    _, imgs = make_images(4, args.unique_images)
+    print(f"[serve] generated {len(imgs)} images in {time.time() - t0:.1f}s", file=sys.stderr,
+          flush=True)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    d_imgs = [torch.from_numpy(im).to(dev) for im in imgs]
+    n_req = args.requests + args.warmup_requests
+    order = [k % len(d_imgs) for k in range(n_req)]
+    settings = dict(wl.settings)
+    cap = settings["max_keypoints"]
+    ex = sm.Extractor(settings)
+    feats = [ex.alloc_features(cap) for _ in range(n_req)]
+    torch.cuda.synchronize()
+    arena = 24 << 30
+
+    def run(arrivals, max_batch, max_inflight):
+        srv = sm.Server(settings, arena_bytes=arena, max_batch=max_batch,
+                        max_inflight=max_inflight)
+        tickets = []
+        start = time.perf_counter()
+        for i in range(n_req):
+            if arrivals is not None:
+                while time.perf_counter() - start < arrivals[i]:
+                    pass
+            tickets.append(srv.submit(d_imgs[order[i]], out=feats[i]))
+        lat = [srv.wait(t)[0] for t in tickets]
+        wall = time.perf_counter() - start
+        stats = srv.stats()
+        srv.close()
+        meas = np.array(lat[args.warmup_requests:])
+        return dict(p50_ms=round(float(np.percentile(meas, 50)), 3),
+                    p99_ms=round(float(np.percentile(meas, 99)), 3),
+                    images_per_s=round(n_req / wall, 2),
+                    batches=stats["batches"], mean_batch=round(n_req / stats["batches"], 2))
+
+    run(None, 64, 2)   # warm-up
+    sat = run(None, 64, 2)
+    sat_rate = sat["images_per_s"]
+    print(f"[serve] saturation {sat_rate} images/s {sat}", file=sys.stderr, flush=True)
+    one = run(None, 1, 1)
+    print(f"[serve] one-at-a-time saturation {one}", file=sys.stderr, flush=True)
+    points = []
+    for k, f in enumerate(float(x) for x in args.qps_fractions.split(",")):
+        qps = f * sat_rate
+        arr = synth.poisson_arrivals(synth.workload_seed(4, 500_000 + k), n_req, qps)
+        batched = run(arr, 64, 2)
+        plain = run(arr, 1, 1)
+        points.append(dict(qps=round(qps, 1), fraction=f, batched=batched, one_at_a_time=plain))
+        print(f"[serve] qps {qps:.1f}: batched {batched} one-at-a-time {plain}", file=sys.stderr,
+              flush=True)
+    mpix = float(np.mean([h * w for h, w in wl.sizes])) / 1e6
+    line = {
+        "metric": "served images/s and p50/p99 latency (continuous batching, Poisson arrivals)",
+        "value": sat_rate, "unit": "images/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "requests": args.requests,
+                   "warmup_requests": args.warmup_requests,
+                   "unique_images": len(imgs), "mean_mpix": round(mpix, 3),
+                   "max_batch": 64, "max_inflight": 2, "arena_gib": arena >> 30},
+        "saturation": sat, "one_at_a_time_saturation": one, "points": points,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +169,13 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0, help="blur tile height (0: library choice)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise pass over MIB MiB (counter yardstick)")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving benchmark instead: Poisson arrivals, W, H ~ U[320, 2048]")
+    ap.add_argument("--requests", type=int, default=700, help="serving: requests per QPS point")
+    ap.add_argument("--warmup-requests", type=int, default=100)
+    ap.add_argument("--unique-images", type=int, default=160,
+                    help="serving: distinct images, cycled over the requests")
+    ap.add_argument("--qps-fractions", default="0.25,0.5,0.75,0.9")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -105,6 +185,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, max(1, args.steps))
+        return
+    if args.serve:
+        serve_bench(args)
         return
 
     import torch

@@ -188,6 +188,56 @@ sift_status sift_profile_start(void);
 sift_status sift_profile_stop(sift_stage_stat* stats, int32_t max_stats, int32_t* n_stats);
 
 /* Static text for a status code. */
+/*
+ * Serving (a request stream of images of any sizes).
+ *
+ * The paper extracts one image per call; this is a continuous-batching
+ * front end over sift_extract_batch.  sift_server_create copies the params,
+ * takes a caller-owned device arena (256-byte aligned; the server carves
+ * per-batch workspaces out of it and never allocates) and starts one host
+ * worker thread bound to the device current at create time.  The worker
+ * repeatedly (1) retires batches whose completion event has fired, freeing
+ * their arena ranges, and (2) while fewer than max_inflight batches are in
+ * flight, admits pending requests in arrival order into one batch as long as
+ * the batch has at most max_batch images and its workspace fits in a free
+ * arena range (admission by footprint), and launches it on one of
+ * max_inflight streams of its own (default priority), so consecutive batches
+ * overlap.  Each request's outputs are bit-identical to sift_extract on the
+ * same image.
+ *
+ * sift_server_submit enqueues a request and returns at once with a ticket;
+ * the image and the output buffers (device) must stay valid and untouched
+ * until the ticket is done.  A request whose workspace alone exceeds the arena
+ * gives SIFT_ERR_TOO_LARGE; size errors are reported as by sift_extract.
+ * sift_server_poll reports whether a ticket is done and, once it is, its
+ * latency (submit to observed completion, milliseconds) and forgets it;
+ * sift_server_wait blocks until the ticket is done, then behaves as poll.
+ * Unknown (or already reported) tickets give SIFT_ERR_INVALID_ARG.
+ * sift_server_destroy finishes every pending and in-flight request, stops the
+ * worker and releases the streams; the arena stays the caller's.  All server
+ * calls are thread-safe.  max_batch 1 and max_inflight 1 serve requests one
+ * at a time in arrival order (the plain per-image path).
+ */
+typedef struct sift_server sift_server;
+
+typedef struct {
+  int64_t submitted;      /* requests accepted */
+  int64_t completed;      /* requests whose batch has finished */
+  int64_t batches;        /* batches launched */
+  int64_t peak_arena;     /* largest arena bytes in use at once */
+  int64_t peak_inflight;  /* largest number of batches in flight at once */
+} sift_server_stats;
+
+sift_status sift_server_create(const sift_params* p, void* d_arena, size_t arena_bytes,
+                               int32_t max_batch, int32_t max_inflight, sift_server** out);
+sift_status sift_server_submit(sift_server* s, const float* d_image, int32_t height,
+                               int32_t width, int64_t pitch, const sift_output* out,
+                               uint64_t* ticket);
+sift_status sift_server_poll(sift_server* s, uint64_t ticket, int32_t* done, double* latency_ms);
+sift_status sift_server_wait(sift_server* s, uint64_t ticket, double* latency_ms);
+sift_status sift_server_get_stats(sift_server* s, sift_server_stats* stats);
+sift_status sift_server_destroy(sift_server* s);
+
 const char* sift_status_string(sift_status st);
 /* Detail of the last error on the calling thread ("" if none). */
 const char* sift_last_error(void);

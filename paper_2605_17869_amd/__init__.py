@@ -3,5 +3,5 @@
 The extraction path is the HIP library ``libsift_mi355x.so`` behind the C ABI
 of ``include/sift.h``; :mod:`.sift` is its Python binding.
 """
-from .sift import (DESC_DIM, KEYPOINT_DTYPE, Extractor, Features, SiftError,  # noqa: F401
+from .sift import (DESC_DIM, KEYPOINT_DTYPE, Extractor, Features, Server, SiftError,  # noqa: F401
                    load_library, make_params, profile_start, profile_stop)

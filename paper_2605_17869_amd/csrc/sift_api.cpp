@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -73,6 +74,11 @@ bool make_taps(double sigma, Taps* t) {
 }
 
 }  // namespace
+
+namespace sift {
+// Sets the text sift_last_error() returns on this thread (used by the server).
+void set_last_error(const std::string& msg) { g_error = msg; }
+}  // namespace sift
 
 struct sift_handle {
   sift_params params;
@@ -154,7 +160,10 @@ struct ProfRecord {
   hipEvent_t a, b;
 };
 
+// Recording is process-wide; the mutex lets extractions from several host
+// threads (e.g. a server's worker) record safely.
 struct Profiler {
+  std::mutex mu;
   bool on = false;
   std::vector<ProfRecord> recs;
   std::vector<hipEvent_t> pool;
@@ -173,6 +182,7 @@ hipEvent_t prof_event() {
 
 // Opens a stage record (no-op when recording is off); close with prof_end.
 int prof_begin(int stage, double bytes, hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   if (!g_prof.on) return -1;
   ProfRecord r;
   r.stage = stage;
@@ -187,6 +197,7 @@ int prof_begin(int stage, double bytes, hipStream_t stream) {
 
 void prof_end(int rec, hipStream_t stream) {
   if (rec < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   hipEventRecord(g_prof.recs[rec].b, stream);
 }
 
@@ -471,12 +482,14 @@ sift_status sift_workspace_level(const sift_handle* h, int32_t height, int32_t w
 }
 
 sift_status sift_profile_start(void) {
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.on = true;
   return SIFT_OK;
 }
 
 sift_status sift_profile_stop(sift_stage_stat* stats, int32_t max_stats, int32_t* n_stats) {
   if (!stats || !n_stats || max_stats < 0) return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(g_prof.mu);
   if (!g_prof.on) return fail(SIFT_ERR_INVALID_ARG, "profiling was not started");
   g_prof.on = false;
   sift_stage_stat tot[kStCount];

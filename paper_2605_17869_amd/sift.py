@@ -62,6 +62,12 @@ KEYPOINT_DTYPE = np.dtype([
 ])
 assert KEYPOINT_DTYPE.itemsize == 48
 
+class SiftServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("peak_arena", ctypes.c_int64),
+                ("peak_inflight", ctypes.c_int64)]
+
+
 # name -> (restype, argtypes)
 _SIGNATURES = {
     "sift_params_default": (ctypes.c_int, [ctypes.POINTER(SiftParams)]),
@@ -93,6 +99,20 @@ _SIGNATURES = {
     "sift_profile_start": (ctypes.c_int, []),
     "sift_profile_stop": (ctypes.c_int, [ctypes.POINTER(SiftStageStat), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),
+    "sift_server_create": (ctypes.c_int, [ctypes.POINTER(SiftParams), ctypes.c_void_p,
+                                          ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "sift_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int64,
+                                          ctypes.POINTER(SiftOutput),
+                                          ctypes.POINTER(ctypes.c_uint64)]),
+    "sift_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_int32),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "sift_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "sift_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SiftServerStats)]),
+    "sift_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sift_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sift_last_error": (ctypes.c_char_p, []),
 }
@@ -303,3 +323,84 @@ class Extractor:
         flat = workspace[off:off + 4 * n].view(torch.float32)
         arr = flat.view(lh.value, lp.value)[:, :lw.value].cpu().numpy().astype(np.float64)
         return arr + 0.5
+
+
+class Server:
+    """Continuous-batching server (``sift_server_*``) over a torch-allocated
+    device arena.  ``submit`` returns a ticket at once; ``wait`` / ``poll``
+    report completion and the request's latency in milliseconds."""
+
+    def __init__(self, settings: dict | None = None, arena_bytes: int = 1 << 32,
+                 max_batch: int = 64, max_inflight: int = 2, **overrides):
+        import torch
+        self.lib = load_library()
+        self.params = make_params(settings, **overrides)
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()   # the arena exists before the worker uses it
+        h = ctypes.c_void_p()
+        _check(self.lib.sift_server_create(ctypes.byref(self.params),
+                                           ctypes.c_void_p(self.arena.data_ptr()),
+                                           int(arena_bytes), int(max_batch), int(max_inflight),
+                                           ctypes.byref(h)), "sift_server_create")
+        self.handle = h
+        self._held = {}   # ticket -> (image, features) kept alive until reported
+
+    def alloc_features(self, capacity: int | None = None) -> Features:
+        import torch
+        cap = int(self.params.max_keypoints if capacity is None else capacity)
+        return Features(torch.empty((max(cap, 1), 12), dtype=torch.int32, device="cuda"),
+                        torch.empty((max(cap, 1), DESC_DIM), dtype=torch.float32, device="cuda"),
+                        torch.zeros(3, dtype=torch.int32, device="cuda"))
+
+    def submit(self, image, out: Features | None = None) -> int:
+        """Enqueue one 2-D float32 CUDA tensor (already written: the caller
+        synchronises its own stream first); returns the ticket."""
+        import torch
+        if image.dim() != 2 or image.dtype != torch.float32 or not image.is_cuda or \
+                image.stride(1) != 1:
+            raise ValueError("image must be a 2-D float32 CUDA tensor with contiguous rows")
+        f = out if out is not None else self.alloc_features()
+        o = Extractor._output(f, f.keypoints.shape[0])
+        t = ctypes.c_uint64()
+        h, w = image.shape
+        _check(self.lib.sift_server_submit(self.handle, ctypes.c_void_p(image.data_ptr()), h, w,
+                                           image.stride(0), ctypes.byref(o), ctypes.byref(t)),
+               "sift_server_submit")
+        self._held[t.value] = (image, f)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(done, latency_ms, features) -- latency and features once done."""
+        done = ctypes.c_int32()
+        lat = ctypes.c_double()
+        _check(self.lib.sift_server_poll(self.handle, ticket, ctypes.byref(done),
+                                         ctypes.byref(lat)), "sift_server_poll")
+        if not done.value:
+            return False, None, None
+        return True, lat.value, self._held.pop(ticket)[1]
+
+    def wait(self, ticket: int):
+        """Block until done; returns (latency_ms, features)."""
+        lat = ctypes.c_double()
+        _check(self.lib.sift_server_wait(self.handle, ticket, ctypes.byref(lat)),
+               "sift_server_wait")
+        return lat.value, self._held.pop(ticket)[1]
+
+    def stats(self) -> dict:
+        st = SiftServerStats()
+        _check(self.lib.sift_server_get_stats(self.handle, ctypes.byref(st)),
+               "sift_server_get_stats")
+        return {k: getattr(st, k) for k, _ in SiftServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            st = self.lib.sift_server_destroy(self.handle)
+            self.handle = None
+            self._held.clear()
+            _check(st, "sift_server_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

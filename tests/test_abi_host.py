@@ -161,3 +161,25 @@ def test_status_strings_and_profile_misuse():
     assert lib.sift_profile_stop(arr, 4, ctypes.byref(n)) == 1
     assert lib.sift_profile_start() == 0
     assert lib.sift_profile_stop(arr, 4, ctypes.byref(n)) == 0 and n.value == 0
+
+
+def test_server_argument_errors_return_before_any_device_call():
+    lib = S.load_library()
+    p = S.make_params()
+    srv = ctypes.c_void_p()
+    # null arena, misaligned arena, batch and in-flight limits
+    assert lib.sift_server_create(ctypes.byref(p), None, 1 << 30, 8, 2, ctypes.byref(srv)) == 1
+    assert lib.sift_server_create(ctypes.byref(p), ctypes.c_void_p(260), 1 << 30, 8, 2,
+                                  ctypes.byref(srv)) == 1
+    assert lib.sift_server_create(ctypes.byref(p), ctypes.c_void_p(256), 1 << 30, 0, 2,
+                                  ctypes.byref(srv)) == 1
+    assert lib.sift_server_create(ctypes.byref(p), ctypes.c_void_p(256), 1 << 30, 8, 9,
+                                  ctypes.byref(srv)) == 1
+    assert b"max_inflight" in lib.sift_last_error()
+    bad = S.make_params(n_scales=0)
+    assert lib.sift_server_create(ctypes.byref(bad), ctypes.c_void_p(256), 1 << 30, 8, 2,
+                                  ctypes.byref(srv)) == 6
+    st = S.SiftServerStats()
+    assert lib.sift_server_get_stats(None, ctypes.byref(st)) == 1
+    assert lib.sift_server_destroy(None) == 0
+    assert ctypes.sizeof(S.SiftServerStats) == 40
