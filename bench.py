@@ -166,7 +166,10 @@ def main():
     ap.add_argument("--per-image-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--tile-rows", type=int, default=0, help="blur tile height (0: library choice)")
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="blur chunk height (0: autotuned on the batch unless --no-autotune)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise pass over MIB MiB (counter yardstick)")
     ap.add_argument("--serve", action="store_true",
@@ -201,31 +204,60 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     d_imgs = [torch.from_numpy(im).to(dev) for im in imgs]
-    settings = dict(wl.settings, tile_rows=args.tile_rows)
-    ex = sm.Extractor(settings)
     sizes = [tuple(im.shape) for im in imgs]
+    stream = torch.cuda.current_stream()
+    tune = None
+    tile_rows = args.tile_rows
+    if tile_rows == 0 and not args.no_autotune:
+        probe = sm.Extractor(wl.settings)
+        ws0 = torch.empty(probe.batch_workspace_size(sizes), dtype=torch.uint8, device=dev)
+        tile_rows, tune_ms = probe.autotune(d_imgs, warmup=1, reps=3, workspace=ws0,
+                                            stream=stream)
+        tune = {str(k): round(v, 4) for k, v in tune_ms.items()}
+        del probe, ws0
+        print(f"[bench] autotune: tile_rows {tile_rows} ({tune})", file=sys.stderr, flush=True)
+    settings = dict(wl.settings, tile_rows=tile_rows)
+    ex = sm.Extractor(settings)
     ws = torch.empty(ex.batch_workspace_size(sizes), dtype=torch.uint8, device=dev)
     outs = [ex.alloc_features() for _ in range(n)]
-    stream = torch.cuda.current_stream()
 
     def batch_step():
         ex.extract_batch(d_imgs, outs=outs, workspace=ws, stream=stream)
 
-    for _ in range(args.warmup):
-        batch_step()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        batch_step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = e0.elapsed_time(e1) / args.steps
-    print(f"[bench] batched: {ms:.3f} ms/step (wall {1e3 * wall / args.steps:.3f})",
+    def timed(step, warmup, steps):
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        wall0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, (time.perf_counter() - wall0) / steps
+
+    ms_eager, wall = timed(batch_step, args.warmup, args.steps)
+    print(f"[bench] batched: {ms_eager:.3f} ms/step (wall {1e3 * wall:.3f})",
           file=sys.stderr, flush=True)
     batch_host = [f.host() for f in outs]
+    ms, mode = ms_eager, "launch sequence"
+
+    # the same batch recorded once as a graph and replayed per step
+    ms_graph, graph_identical = None, None
+    if not args.no_graph:
+        outs_g = [ex.alloc_features() for _ in range(n)]
+        ws_g = torch.empty_like(ws)
+        g = ex.graph(d_imgs, outs=outs_g, workspace=ws_g)
+        ms_graph, wall_g = timed(lambda: g.launch(stream), args.warmup, args.steps)
+        graph_identical = all(digest(a[0], a[1]) == digest(b[0], b[1]) and a[2:] == b[2:]
+                              for a, b in zip(batch_host, [f.host() for f in outs_g]))
+        g.close()
+        del ws_g, outs_g
+        print(f"[bench] graph replay: {ms_graph:.3f} ms/step, identical={graph_identical}",
+              file=sys.stderr, flush=True)
+        if graph_identical and ms_graph < ms:
+            ms, mode = ms_graph, "graph replay"
 
     # plain per-image path on the same images
     ms1, identical = None, None
@@ -238,13 +270,7 @@ def main():
                 ex.extract(d_imgs[k], out=outs1[k], workspace=ws1, stream=stream)
 
         per_image_step()
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(args.per_image_steps):
-            per_image_step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms1 = e0.elapsed_time(e1) / args.per_image_steps
+        ms1, _ = timed(per_image_step, 0, args.per_image_steps)
         single_host = [f.host() for f in outs1]
         identical = all(digest(a[0], a[1]) == digest(b[0], b[1]) and a[2:] == b[2:]
                         for a, b in zip(batch_host, single_host))
@@ -303,12 +329,17 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "images": n, "image_size": f"{sizes[0][1]}x{sizes[0][0]}",
-                   "tile_rows": args.tile_rows, "upsample": wl.settings["upsample"], "octaves": wl.settings["n_octaves"] +
+                   "tile_rows": tile_rows, "upsample": wl.settings["upsample"], "octaves": wl.settings["n_octaves"] +
                    wl.settings["upsample"], "parallelism": "none (one GPU)"},
         "mpix_per_s": round(mpix / (ms * 1e-3), 2),
         "per_image_path": ({"images_per_s": round(n / (ms1 * 1e-3), 2),
                             "ms_per_step": round(ms1, 4)} if ms1 else None),
         "batched_vs_per_image": round(ms1 / ms, 3) if ms1 else None,
+        "execution": mode,
+        "ms_per_step_launch_sequence": round(ms_eager, 4),
+        "ms_per_step_graph_replay": round(ms_graph, 4) if ms_graph else None,
+        "bitwise_identical_graph_vs_launch_sequence": graph_identical,
+        "autotune_ms_per_tile_rows": tune,
         "bitwise_identical_batched_vs_per_image": identical,
         "keypoints_per_image": round(n_kp / n, 1),
         "stages": stages,

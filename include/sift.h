@@ -189,6 +189,43 @@ sift_status sift_profile_stop(sift_stage_stat* stats, int32_t max_stats, int32_t
 
 /* Static text for a status code. */
 /*
+ * Replayable batches (HIP graphs).  For a batch whose shapes and buffers
+ * repeat (one graph per size bucket), sift_graph_create records the whole
+ * launch sequence of sift_extract_batch with these exact arguments into a HIP
+ * graph, on a private stream (nothing runs at create time), and
+ * sift_graph_launch replays it on `stream` with one call.  A replay reads the
+ * images at the recorded addresses as they are when it runs, so the caller
+ * rewrites them in place between replays; the workspace and outputs are the
+ * recorded ones and must not be in use by anything else while a replay is in
+ * flight.  Results are bit-identical to sift_extract_batch.  Stage profiling
+ * does not see replays.
+ */
+typedef struct sift_graph sift_graph;
+
+sift_status sift_graph_create(sift_handle* h, int32_t n, const float* const* d_images,
+                              const int32_t* heights, const int32_t* widths,
+                              const int64_t* pitches, void* d_workspace, size_t workspace_bytes,
+                              const sift_output* outs, sift_graph** out);
+sift_status sift_graph_launch(sift_graph* g, void* stream);
+sift_status sift_graph_destroy(sift_graph* g);
+
+/*
+ * Tuning.  sift_autotune_batch times sift_extract_batch on the given batch
+ * for every blur chunk height (64, 128, 256, 512 rows; all give bit-identical
+ * results) and returns the fastest in *best_tile_rows and the mean time of
+ * each candidate, in that order, in ms[4] (host, may be NULL).  It runs
+ * `warmup` untimed and `reps` timed extractions per candidate on `stream` and
+ * waits for them (it synchronises; it is not for a capture or a hot loop).
+ * Set the result as sift_params.tile_rows of the handle used afterwards.
+ */
+sift_status sift_autotune_batch(const sift_params* p, int32_t n, const float* const* d_images,
+                                const int32_t* heights, const int32_t* widths,
+                                const int64_t* pitches, void* d_workspace,
+                                size_t workspace_bytes, const sift_output* outs, void* stream,
+                                int32_t warmup, int32_t reps, int32_t* best_tile_rows,
+                                float* ms);
+
+/*
  * Serving (a request stream of images of any sizes).
  *
  * The paper extracts one image per call; this is a continuous-batching

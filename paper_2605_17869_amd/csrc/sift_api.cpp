@@ -23,6 +23,8 @@ using namespace sift;
 namespace {
 
 thread_local std::string g_error;
+// Set while this thread records a launch sequence into a graph: no events then.
+thread_local bool g_capturing = false;
 
 sift_status fail(sift_status st, const char* fmt, ...) {
   char buf[512];
@@ -78,6 +80,8 @@ bool make_taps(double sigma, Taps* t) {
 namespace sift {
 // Sets the text sift_last_error() returns on this thread (used by the server).
 void set_last_error(const std::string& msg) { g_error = msg; }
+// Marks this thread as recording a graph (stage profiling skips it).
+void set_capturing(bool on) { g_capturing = on; }
 }  // namespace sift
 
 struct sift_handle {
@@ -182,6 +186,7 @@ hipEvent_t prof_event() {
 
 // Opens a stage record (no-op when recording is off); close with prof_end.
 int prof_begin(int stage, double bytes, hipStream_t stream) {
+  if (g_capturing) return -1;
   std::lock_guard<std::mutex> lk(g_prof.mu);
   if (!g_prof.on) return -1;
   ProfRecord r;

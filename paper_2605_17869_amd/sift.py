@@ -113,6 +113,24 @@ _SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_double)]),
     "sift_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SiftServerStats)]),
     "sift_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sift_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_void_p),
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
+                                         ctypes.c_size_t, ctypes.POINTER(SiftOutput),
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "sift_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sift_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sift_autotune_batch": (ctypes.c_int, [ctypes.POINTER(SiftParams), ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
+                                           ctypes.c_size_t, ctypes.POINTER(SiftOutput),
+                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_float)]),
     "sift_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sift_last_error": (ctypes.c_char_p, []),
 }
@@ -283,11 +301,9 @@ class Extractor:
                                      _stream_handle(stream)), "sift_extract")
         return f
 
-    def extract_batch(self, images, capacity: int | None = None, outs=None, workspace=None,
-                      stream=None) -> list:
-        """Enqueue extraction of a list of 2-D float32 CUDA tensors in one batch."""
-        n = len(images)
+    def _batch_args(self, images, capacity, outs, workspace):
         import torch
+        n = len(images)
         for im in images:
             if im.dim() != 2 or im.dtype != torch.float32 or not im.is_cuda or im.stride(1) != 1:
                 raise ValueError("images must be 2-D CUDA tensors with contiguous rows")
@@ -301,11 +317,40 @@ class Extractor:
         pitches = (ctypes.c_int64 * n)(*[im.stride(0) for im in images])
         o = (SiftOutput * n)(*[self._output(f, f.keypoints.shape[0] if capacity is None
                                             else int(capacity)) for f in feats])
-        _check(self.lib.sift_extract_batch(self.handle, n, ptrs, hs, wss, pitches,
-                                           ctypes.c_void_p(ws.data_ptr()),
-                                           ws.numel() * ws.element_size(), o,
-                                           _stream_handle(stream)), "sift_extract_batch")
+        return (n, ptrs, hs, wss, pitches, ctypes.c_void_p(ws.data_ptr()),
+                ws.numel() * ws.element_size(), o), feats, ws
+
+    def extract_batch(self, images, capacity: int | None = None, outs=None, workspace=None,
+                      stream=None) -> list:
+        """Enqueue extraction of a list of 2-D float32 CUDA tensors in one batch."""
+        args, feats, _ = self._batch_args(images, capacity, outs, workspace)
+        _check(self.lib.sift_extract_batch(self.handle, *args, _stream_handle(stream)),
+               "sift_extract_batch")
         return feats
+
+    def graph(self, images, capacity: int | None = None, outs=None, workspace=None):
+        """Record the batch's launch sequence into a replayable graph (the
+        images are read at their current addresses on every replay)."""
+        import torch
+        if workspace is None:   # a graph owns its workspace: replays must not share it
+            workspace = torch.empty(self.batch_workspace_size([tuple(im.shape) for im in images]),
+                                    dtype=torch.uint8, device="cuda")
+        args, feats, ws = self._batch_args(images, capacity, outs, workspace)
+        g = ctypes.c_void_p()
+        _check(self.lib.sift_graph_create(self.handle, *args, ctypes.byref(g)),
+               "sift_graph_create")
+        return BatchGraph(self.lib, g, list(images), feats, ws)
+
+    def autotune(self, images, warmup: int = 1, reps: int = 3, outs=None, workspace=None,
+                 stream=None):
+        """(best tile_rows, {tile_rows: ms}) for this batch; see sift_autotune_batch."""
+        args, _, _ = self._batch_args(images, None, outs, workspace)
+        best = ctypes.c_int32()
+        ms = (ctypes.c_float * 4)()
+        _check(self.lib.sift_autotune_batch(ctypes.byref(self.params), *args,
+                                            _stream_handle(stream), warmup, reps,
+                                            ctypes.byref(best), ms), "sift_autotune_batch")
+        return best.value, dict(zip((64, 128, 256, 512), list(ms)))
 
     def level(self, workspace, height: int, width: int, octave: int, level: int):
         """Gaussian level (octave, level) of the last single-image extraction in
@@ -323,6 +368,31 @@ class Extractor:
         flat = workspace[off:off + 4 * n].view(torch.float32)
         arr = flat.view(lh.value, lp.value)[:, :lw.value].cpu().numpy().astype(np.float64)
         return arr + 0.5
+
+
+class BatchGraph:
+    """A recorded batch (``sift_graph_*``); keeps its buffers alive."""
+
+    def __init__(self, lib, handle, images, feats, workspace):
+        self.lib, self.handle = lib, handle
+        self.images, self.features, self._ws = images, feats, workspace
+
+    def launch(self, stream=None):
+        _check(self.lib.sift_graph_launch(self.handle, _stream_handle(stream)),
+               "sift_graph_launch")
+        return self.features
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            st = self.lib.sift_graph_destroy(self.handle)
+            self.handle = None
+            _check(st, "sift_graph_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

@@ -183,3 +183,17 @@ def test_server_argument_errors_return_before_any_device_call():
     assert lib.sift_server_get_stats(None, ctypes.byref(st)) == 1
     assert lib.sift_server_destroy(None) == 0
     assert ctypes.sizeof(S.SiftServerStats) == 40
+
+
+def test_graph_and_autotune_argument_errors():
+    lib = S.load_library()
+    assert lib.sift_graph_launch(None, None) == 1
+    assert lib.sift_graph_destroy(None) == 0
+    g = ctypes.c_void_p()
+    assert lib.sift_graph_create(None, 1, None, None, None, None, None, 0, None, None) == 1
+    best = ctypes.c_int32()
+    p = S.make_params()
+    assert lib.sift_autotune_batch(None, 1, None, None, None, None, None, 0, None, None, 1, 3,
+                                   ctypes.byref(best), None) == 1
+    assert lib.sift_autotune_batch(ctypes.byref(p), 1, None, None, None, None, None, 0, None,
+                                   None, 1, 0, ctypes.byref(best), None) == 1

@@ -1,0 +1,56 @@
+"""Replayable batches (sift_graph_*) and the chunk-height autotuner through
+the C ABI.  Each replay re-reads the images in place: the test rewrites them
+between replays, runs eager extractions in between, and checks every replay
+against eager extraction bit for bit.  Needs an MI355X."""
+import numpy as np
+import pytest
+
+from paper_2605_17869_amd import synth
+from gpu_util import digest, extract, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+SETTINGS = dict(synth.BASE_SETTINGS, n_octaves=3, upsample=1)
+SIZES = [(120, 160), (200, 150), (96, 300)]
+
+
+def images(seed):
+    return [synth.blob_image(seed * 10 + k, h, w, max(1, int(h * w * 3 * synth.BLOB_DENSITY)))
+            for k, (h, w) in enumerate(SIZES)]
+
+
+def test_graph_replays_match_eager_extraction():
+    torch = require_gpu()
+    from paper_2605_17869_amd import Extractor
+    ex = Extractor(SETTINGS)
+    bufs = [torch.from_numpy(im).cuda() for im in images(1)]
+    torch.cuda.synchronize()
+    g = ex.graph(bufs)
+    for rnd, seed in enumerate((1, 2, 3, 2)):
+        new = images(seed)
+        for b, im in zip(bufs, new):
+            b.copy_(torch.from_numpy(im))
+        ref = [extract(ex, im) for im in new]    # eager work between replays
+        feats = g.launch()
+        torch.cuda.synchronize()
+        for k, f in enumerate(feats):
+            kp, desc, nf, nc = f.host()
+            assert digest(kp, desc) == digest(ref[k][0], ref[k][1]), (rnd, k)
+            assert (nf, nc) == ref[k][2:], (rnd, k)
+            if rnd == 0:
+                assert len(kp) > 5
+        say(f"replay {rnd} (seed {seed}) matches eager")
+    g.close()
+
+
+def test_autotune_picks_a_candidate():
+    torch = require_gpu()
+    from paper_2605_17869_amd import Extractor
+    ex = Extractor(SETTINGS)
+    bufs = [torch.from_numpy(im).cuda() for im in images(4)]
+    torch.cuda.synchronize()
+    best, ms = ex.autotune(bufs, warmup=1, reps=2)
+    say(f"autotune: best {best}, {ms}")
+    assert best in (64, 128, 256, 512)
+    assert all(v > 0 for v in ms.values())
+    assert ms[best] == min(ms.values())
