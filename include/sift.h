@@ -44,7 +44,9 @@ typedef enum {
   SIFT_ERR_INVALID_ARG = 1,         /* null pointer, bad parameter, h/w <= 0, pitch < w */
   SIFT_ERR_IMAGE_TOO_SMALL = 2,     /* last octave would have min(h, w) < 2*border + 3 */
   SIFT_ERR_WORKSPACE_TOO_SMALL = 3, /* workspace_bytes below what *_workspace_size gives */
-  SIFT_ERR_TOO_LARGE = 4,           /* image or batch beyond the library's index limits */
+  SIFT_ERR_TOO_LARGE = 4,           /* image or batch beyond the library's index limits (side
+                                       above 32768, a pyramid level of 2 GiB or more, batch
+                                       above 4096) */
   SIFT_ERR_HIP = 5,                 /* HIP runtime error; sift_last_error() has the text */
   SIFT_ERR_NOT_SUPPORTED = 6        /* a parameter value the kernels do not implement */
 } sift_status;

@@ -137,6 +137,11 @@ sift_status validate_size(const sift_handle* h, int height, int width) {
   if (height > kMaxSide || width > kMaxSide)
     return fail(SIFT_ERR_TOO_LARGE, "image side above %d", kMaxSide);
   int hk, wk;
+  // kernels address a level with 32-bit byte offsets: the first (largest)
+  // level plane must stay below 2 GiB
+  octave_dims(height, width, h->dev.upsample, 0, &hk, &wk);
+  if ((int64_t)hk * level_pitch(wk) * 4 >= (int64_t(1) << 31))
+    return fail(SIFT_ERR_TOO_LARGE, "a %dx%d level exceeds 2 GiB", hk, wk);
   octave_dims(height, width, h->dev.upsample, h->dev.n_oct - 1, &hk, &wk);
   const int need = 2 * h->dev.border + 3;
   if (hk < need || wk < need)

@@ -576,6 +576,8 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
     const OctView ov = octave_view(e.h, e.w, lc, k);
     const int hk = ov.h, wk = ov.w, pk = ov.pitch;
     const float* L = level_ptr(ws, e, ov, kp.layer);
+    const gchar* gL = uniform_ptr(reinterpret_cast<const gchar*>(as_global(L)));
+    const uint32_t pkb = (uint32_t)pk * 4u;
     const float th = angle * (kTwoPi / 360.0f);
     const float st = sinf(th), ct = cosf(th);
 
@@ -591,6 +593,7 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
       const int R = (int)ceilf(2.5f * wc * (fabsf(ct) + fabsf(st))) + 1;
       const int side = 2 * R + 1;
       const int nsamp = side * side;
+      const float inv_side = 1.0f / (float)side;
 
       // rotated, cell-scaled coordinates of offset (dx, dy)
       auto rotate = [&](int dx, int dy, float& xr, float& yr) {
@@ -615,38 +618,48 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
         const float wgt = mag * exp_fast(-(xr * xr + yr * yr) * 0.125f);
         const float r0 = floorf(rb), c0 = floorf(cb), o0 = floorf(ob);
         const float fr = rb - r0, fc = cb - c0, fo = ob - o0;
-        const int ir = (int)r0, ic = (int)c0;
+        const int ir = (int)r0, ic = (int)c0;   // in -1..3
         int io = (int)o0;
         if (io >= 8) io -= 8;
-        // The 2 x 2 cells around (rb, cb), orientations io and io + 1.  A
-        // cell outside the 4 x 4 grid adds +0 to orientations io + 4 and
-        // io + 5 of the nearest grid cell: those are never among the other
-        // targets, and adding +0 to a non-negative sum leaves it unchanged.
-        // The eight targets of one sample are thus read first, then written.
-        float wv[8];
-        int bv[8];
+        const int io1 = (io + 1) & 7;
+        // The sample spreads over rows ir, ir + 1 (weights 1 - fr, fr) and
+        // columns ic, ic + 1 of the 4 x 4 grid, orientations io and io + 1.
+        // It updates the 2 x 2 grid cells from (rr0, cc0) = (ir, ic) clamped
+        // to 0..2, so the eight targets are always on the grid and distinct:
+        // a target row or column the sample does not reach gets weight +0,
+        // and adding +0 to a non-negative sum leaves it unchanged.  The
+        // eight targets are read first, then written.
+        const int rr0 = min(max(ir, 0), 2), cc0 = min(max(ic, 0), 2);
+        const float wr0 = ir == rr0 ? 1.0f - fr : (ir < rr0 ? fr : 0.0f);
+        const float wr1 = ir == rr0 ? fr : (ir < rr0 ? 0.0f : 1.0f - fr);
+        const float wc0 = ic == cc0 ? 1.0f - fc : (ic < cc0 ? fc : 0.0f);
+        const float wc1 = ic == cc0 ? fc : (ic < cc0 ? 0.0f : 1.0f - fc);
+        const float wa[2] = {wgt * wr0, wgt * wr1};
+        const float wb[2] = {wc0, wc1};
+        float* h0 = &hist[((rr0 * 4 + cc0) * 8 + io) * 64 + lane];
+        float* h1 = &hist[((rr0 * 4 + cc0) * 8 + io1) * 64 + lane];
+        float hv[8], wv[8];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
-          const int row_b = ir + a;
-          const float wr = a ? fr : 1.0f - fr;
 #pragma unroll
           for (int bb = 0; bb < 2; ++bb) {
-            const int col_b = ic + bb;
-            const bool in = row_b >= 0 && row_b <= 3 && col_b >= 0 && col_b <= 3;
-            const int cell = (min(max(row_b, 0), 3) * 4 + min(max(col_b, 0), 3)) * 8;
-            const int oa = in ? io : (io + 4) & 7;
-            const float w2 = wgt * wr * (bb ? fc : 1.0f - fc);
-            wv[4 * a + 2 * bb] = in ? w2 * (1.0f - fo) : 0.0f;
-            wv[4 * a + 2 * bb + 1] = in ? w2 * fo : 0.0f;
-            bv[4 * a + 2 * bb] = (cell + oa) * 64 + lane;
-            bv[4 * a + 2 * bb + 1] = (cell + ((oa + 1) & 7)) * 64 + lane;
+            const int off = (a * 4 + bb) * 8 * 64;   // cell step: 8 bins of 64 lanes
+            const float w2 = wa[a] * wb[bb];
+            wv[4 * a + 2 * bb] = w2 * (1.0f - fo);
+            wv[4 * a + 2 * bb + 1] = w2 * fo;
+            hv[4 * a + 2 * bb] = h0[off];
+            hv[4 * a + 2 * bb + 1] = h1[off];
           }
         }
-        float hv[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) hv[c] = hist[bv[c]];
+        for (int a = 0; a < 2; ++a) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) hist[bv[c]] = hv[c] + wv[c];
+          for (int bb = 0; bb < 2; ++bb) {
+            const int off = (a * 4 + bb) * 8 * 64;
+            h0[off] = hv[4 * a + 2 * bb] + wv[4 * a + 2 * bb];
+            h1[off] = hv[4 * a + 2 * bb + 1] + wv[4 * a + 2 * bb + 1];
+          }
+        }
       };
 
       // Pending contributing samples sit in lanes [0, fill): packed offset
@@ -662,7 +675,9 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int qq = q0 + 64 * u + lane;
-          const int qy = qq / side;
+          // qq / side through fp32: exact for side < 2048 (the quotient is
+          // at least 0.5 / side away from an integer)
+          const int qy = (int)(((float)qq + 0.5f) * inv_side);
           const int dy = qy - R, dx = qq - qy * side - R;
           const int rr = kp.r + dy, cc = kp.c + dx;
           float xr, yr;
@@ -672,11 +687,11 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
                   rb > -1.0f && rb < 4.0f && cb > -1.0f && cb < 4.0f;
           sxy[u] = (dy << 16) | (dx & 0xffff);
           // samples that do not contribute read the (interior) centre instead
-          const float* row = L + (int64_t)(ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c);
-          ga[u] = row[1];
-          gb[u] = row[-1];
-          gc[u] = row[pk];
-          gd[u] = row[-pk];
+          const uint32_t at = (uint32_t)((ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c)) * 4u;
+          ga[u] = load_at(gL, at + 4u);
+          gb[u] = load_at(gL, at - 4u);
+          gc[u] = load_at(gL, at + pkb);
+          gd[u] = load_at(gL, at - pkb);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {

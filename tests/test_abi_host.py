@@ -110,6 +110,10 @@ def test_workspace_size_rules():
     with pytest.raises(S.SiftError) as ei:
         ex.workspace_size(40000, 100)
     assert ei.value.status == 4
+    with pytest.raises(S.SiftError) as ei:     # a 3.6 GB level
+        ex.workspace_size(30000, 30000)
+    assert ei.value.status == 4
+    assert S.Extractor(upsample=1).workspace_size(11000, 11000) > 0
     up = S.Extractor(upsample=1)
     assert up.workspace_size(480, 640) > 2 * n
     b = ex.batch_workspace_size([(480, 640), (300, 200)])
