@@ -4,28 +4,33 @@
 // explicitly, so the level values are the same whatever the launch shape.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "sift_device.h"
 #include "sift_launch.h"
 
 namespace sift {
 
 // ---------------------------------------------------------------------------
-// Gaussian level: separable blur, one work-group per strip of kTileW columns
-// and up to `th` rows of one image.  The group walks down its strip in steps
-// of B = kBlurRows rows: it stages B source rows (plus an R-column mirrored
-// halo) in LDS, runs the horizontal pass over them into a ring of horizontally
-// blurred rows, and runs the vertical pass over the ring to emit B output
-// rows.  Each source row is staged once per strip and each horizontal result
-// computed once, so apart from the 2R-row lead-in at the top of a chunk there
-// is no halo recomputation.  Source rows of the next step are fetched into
-// registers while the current step computes.
+// Gaussian level: separable blur, one work-group of 256 threads per strip of
+// kTileW = 192 output columns and up to `th` rows of one image.  The group
+// walks down its strip in steps of B = kBlurRows rows.  Vertical pass first:
+// thread t owns source column x0 - R + t (192 + 2R <= 256 of them) and keeps
+// a sliding window of 2R + B source rows of that column in registers, so each
+// source pixel is loaded once per strip and the next step's rows are fetched
+// while the current step computes; it writes B vertically blurred values to
+// an LDS block (two blocks, alternating, so one barrier per step suffices).
+// Horizontal pass: 3 tasks per thread, each reading 4 + 2R values of a row
+// from the block and writing 4 consecutive outputs; tasks run along the rows
+// so a wave's stores cover contiguous memory.
 //
 // Each output is
-//   acc = 0; for t = 0..2R: acc = fma(g[t], in[x - R + t], acc)
-// for the horizontal pass and the same along columns for the vertical pass,
-// whatever the strip or chunk shape.  Levels are held relative to mid-grey
-// (L - 0.5): the blur is linear with unit-sum taps, so this changes no
-// difference of levels and keeps fp32 rounding error proportional to |L - 0.5|.
+//   acc = 0; for t = 0..2R: acc = fma(g[t], in[y - R + t], acc)
+// down the column for the vertical pass and the same along the row for the
+// horizontal pass, whatever the strip or chunk shape.  Levels are held
+// relative to mid-grey (L - 0.5): the blur is linear with unit-sum taps, so
+// this changes no difference of levels and keeps fp32 rounding error
+// proportional to |L - 0.5|.
 //
 // Work-groups are dealt round-robin to the 8 XCDs, each with its own L2; the
 // grid is a multiple of 8 and group b takes work item (b % 8) * (grid / 8) +
@@ -39,21 +44,22 @@ constexpr int lds_stride4(int n) {
 }
 
 // UP selects the source of level 0 of the upsampled octave (bilinear 2x of
-// the input image); otherwise a source pixel is src[y * sp + x * sx] - bias.
+// the input image); otherwise a source pixel is src[y * sp + (x << csh)] - bias.
 template <int R, bool UP>
-__global__ __launch_bounds__(kTileW) void k_blur(BlurArgs a) {
-  constexpr int TW = kTileW;          // output columns; one thread per column
+__global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
+  constexpr int TW = kTileW;          // output columns of the strip
+  constexpr int NT = kBlurThreads;
   constexpr int B = kBlurRows;        // rows per step
-  constexpr int HB = 16;              // horizontal outputs per thread
-  constexpr int WI = TW + 2 * R;      // staged source columns
+  constexpr int HB = 4;               // horizontal outputs per task
+  constexpr int NQ = TW / HB;         // horizontal tasks per row
+  constexpr int NREP = NQ * kBlurRows / kBlurThreads;   // tasks per thread
+  constexpr int WI = TW + 2 * R;      // source columns of the strip
   constexpr int SS = lds_stride4(WI);
-  constexpr int RS = lds_stride4(TW);
-  constexpr int NB = (2 * R + B - 1) / B + 1;   // ring blocks of B rows
-  constexpr int NH = (2 * R + HB + 3) / 4;      // float4 reads per horizontal task
-  static_assert((TW / HB) * B == TW, "one horizontal task per thread");
-  static_assert(TW + 2 * R <= 2 * TW, "two staged columns per thread");
-  __shared__ __align__(16) float s_in[B * SS];
-  __shared__ __align__(16) float s_ring[NB * B * RS];
+  constexpr int W = 2 * R + B;        // vertical window (rows)
+  constexpr int NH = (2 * R + HB + 3) / 4;   // float4 reads per horizontal task
+  static_assert(NREP * NT == NQ * B, "whole horizontal tasks per thread");
+  static_assert(WI <= NT, "one source column per thread");
+  __shared__ __align__(16) float s_v[2][B * SS];
 
   const int* tp = a.tile_prefix;
   const int per_xcd = gridDim.x / kXcds;
@@ -75,13 +81,13 @@ __global__ __launch_bounds__(kTileW) void k_blur(BlurArgs a) {
   const int t = threadIdx.x;
   const int mode = a.mode;
 
-  // ---- per-thread source columns (staged columns t and t + TW)
-  const bool has1 = t + TW < WI;
-  const int xc0 = mirror(x0 - R + t, wk);
-  const int xc1 = has1 ? mirror(x0 - R + t + TW, wk) : xc0;
+  // ---- the thread's source column (threads past the strip's columns repeat
+  // the last one; their values are never read)
+  const int xs = x0 - R + min(t, WI - 1);
+  const int xc = mirror(xs, wk);
   const float* src;
   int64_t sp;          // source row pitch in bytes
-  int csh;             // source column = staged column << csh
+  int csh;             // source column = xc << csh
   float bias = 0.0f;
   if (UP || mode == kSrcImage) {
     src = e.src;
@@ -100,152 +106,119 @@ __global__ __launch_bounds__(kTileW) void k_blur(BlurArgs a) {
     csh = 1;
   }
   const gchar* gsrc = uniform_ptr(reinterpret_cast<const gchar*>(as_global(src)));
-  const uint32_t bo0 = (uint32_t)(xc0 << csh) * 4u, bo1 = (uint32_t)(xc1 << csh) * 4u;
+  const uint32_t bo = (uint32_t)(xc << csh) * 4u;
   // bilinear 2x upsampling: U[y][x] = I(y/2, x/2), the sample past the last
   // row or column clamped to it; computed on centred values
-  const uint32_t ua0 = (uint32_t)(xc0 >> 1) * 4u, ub0 = (uint32_t)min((xc0 >> 1) + 1, e.w - 1) * 4u;
-  const uint32_t ua1 = (uint32_t)(xc1 >> 1) * 4u, ub1 = (uint32_t)min((xc1 >> 1) + 1, e.w - 1) * 4u;
-  const bool uo0 = xc0 & 1, uo1 = xc1 & 1;
+  const uint32_t ua = (uint32_t)(xc >> 1) * 4u, ub = (uint32_t)min((xc >> 1) + 1, e.w - 1) * 4u;
+  const bool uo = xc & 1;
 
-  // H-row h (h = 0 is image row y0 - R) belongs to block h / B
-  const int M = cdiv(y1 - y0, B);     // output steps
-  const int NBLK = M + NB - 1;        // horizontal blocks
-  float v0[B], v1[B];
-  // Loads are issued unconditionally (lanes without a second column reload
-  // their first) and blended afterwards, so no load sits under a branch that
-  // would force an early wait for it.
-  auto fetch_row = [&](int y, int r) {
+  // source value of (mirrored) row y at the thread's column; loads are not
+  // under a branch, so none forces an early wait
+  auto fetch = [&](int y) -> float {
     if (UP) {
       const int ya = y >> 1, yb = min(ya + 1, e.h - 1);
       const gchar* r0 = uniform_ptr(gsrc + ya * sp);
       const gchar* r1 = uniform_ptr(gsrc + ((y & 1) ? yb : ya) * sp);
-      const float a0 = load_at(r0, ua0), b0 = load_at(r0, ub0);
-      const float c0 = load_at(r1, ua0), d0 = load_at(r1, ub0);
-      const float a1 = load_at(r0, ua1), b1 = load_at(r0, ub1);
-      const float c1 = load_at(r1, ua1), d1 = load_at(r1, ub1);
-      float top0 = a0 - bias, bot0 = c0 - bias, top1 = a1 - bias, bot1 = c1 - bias;
-      top0 = uo0 ? (top0 + (b0 - bias)) * 0.5f : top0;
-      bot0 = uo0 ? (bot0 + (d0 - bias)) * 0.5f : bot0;
-      top1 = uo1 ? (top1 + (b1 - bias)) * 0.5f : top1;
-      bot1 = uo1 ? (bot1 + (d1 - bias)) * 0.5f : bot1;
-      v0[r] = (y & 1) ? (top0 + bot0) * 0.5f : top0;
-      v1[r] = (y & 1) ? (top1 + bot1) * 0.5f : top1;
+      const float va = load_at(r0, ua), vb = load_at(r0, ub);
+      const float vc = load_at(r1, ua), vd = load_at(r1, ub);
+      float top = va - bias, bot = vc - bias;
+      top = uo ? (top + (vb - bias)) * 0.5f : top;
+      bot = uo ? (bot + (vd - bias)) * 0.5f : bot;
+      return (y & 1) ? (top + bot) * 0.5f : top;
     } else {
-      const gchar* row = uniform_ptr(gsrc + y * sp);
-      v0[r] = load_at(row, bo0) - bias;
-      v1[r] = load_at(row, bo1) - bias;
+      return load_at(uniform_ptr(gsrc + y * sp), bo) - bias;
     }
   };
-  auto load_block = [&](int beta) {
-    const int ybase = y0 - R + beta * B;
-    if (ybase >= 0 && ybase + B <= hk) {
+  // n consecutive rows from image row ybase (mirrored at the borders)
+  auto fetch_rows = [&](float* dst, int ybase, auto n_c) {
+    constexpr int n = decltype(n_c)::value;
+    if (ybase >= 0 && ybase + n <= hk) {
 #pragma unroll
-      for (int r = 0; r < B; ++r) fetch_row(ybase + r, r);
+      for (int r = 0; r < n; ++r) dst[r] = fetch(ybase + r);
     } else {
 #pragma unroll
-      for (int r = 0; r < B; ++r) fetch_row(mirror(ybase + r, hk), r);
+      for (int r = 0; r < n; ++r) dst[r] = fetch(mirror(ybase + r, hk));
     }
   };
+
+  // window w[i] = source row y0 + m B - R + i of the thread's column
+  float w[W];
+  float pre[B];
+  fetch_rows(w, y0 - R, std::integral_constant<int, W>());
   gchar* l0 = nullptr;
   if (!UP && mode == kSrcDown)
     l0 = uniform_ptr(reinterpret_cast<gchar*>(as_global(level_ptr(a.ws, e, ov, 0))));
-  const int xend = min(x0 + TW, wk);
+  const bool own_col = t >= R && t < R + TW && xs < wk;
   const int64_t pkb = 4 * (int64_t)pk;
-  auto store_block = [&](int beta) {
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-      s_in[r * SS + t] = v0[r];
-      if (has1) s_in[r * SS + t + TW] = v1[r];
-    }
-    if (!UP && mode == kSrcDown) {
+  const int M = cdiv(y1 - y0, B);     // steps
+
+  for (int m = 0; m < M; ++m) {
+    const int yb = y0 + m * B;
+    if (m + 1 < M) fetch_rows(pre, yb + B + R, std::integral_constant<int, B>());
+    if (!UP && mode == kSrcDown && own_col) {
       // the subsampled base is this octave's level 0: written by the chunk
       // that owns the row and the strip that owns the column
-      const int xa = x0 - R + t, xb = xa + TW;
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+        if (yb + r < y1) store_at(uniform_ptr(l0 + (yb + r) * pkb), (uint32_t)xs * 4u, w[R + r]);
+    }
+    // vertical pass into LDS block m & 1 (threads past the strip's source
+    // columns have nothing to write: their row offset would run past SS)
+    float* blk = s_v[m & 1];
+    if (t < WI) {
+#pragma unroll
       for (int r = 0; r < B; ++r) {
-        const int y = y0 - R + beta * B + r;
-        if (y >= y0 && y < y1) {
-          gchar* row = uniform_ptr(l0 + y * pkb);
-          if (xa >= x0 && xa < xend) store_at(row, (uint32_t)xa * 4u, v0[r]);
-          if (has1 && xb < xend) store_at(row, (uint32_t)xb * 4u, v1[r]);
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q <= 2 * R; ++q) acc = __fmaf_rn(a.taps[q], w[r + q], acc);
+        blk[r * SS + t] = acc;
+      }
+    }
+    __syncthreads();
+    // horizontal pass: tasks of 4 consecutive outputs, numbered along the
+    // rows so that consecutive lanes write consecutive 16-byte pieces
+#pragma unroll
+    for (int rep = 0; rep < NREP; ++rep) {
+      const int task = rep * NT + t;
+      const int hr = task / NQ, hq = task - (task / NQ) * NQ;
+      const float4* in = reinterpret_cast<const float4*>(&blk[hr * SS + hq * HB]);
+      float acc[HB];
+#pragma unroll
+      for (int j = 0; j < HB; ++j) acc[j] = 0.0f;
+#pragma unroll
+      for (int j4 = 0; j4 < NH; ++j4) {
+        const float4 q = in[j4];
+        const float qv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int jj = 4 * j4 + u;
+#pragma unroll
+          for (int j = 0; j < HB; ++j) {
+            const int tt = jj - j;
+            if (tt >= 0 && tt <= 2 * R) acc[j] = __fmaf_rn(a.taps[tt], qv[u], acc[j]);
+          }
+        }
+      }
+      const int y = yb + hr;
+      const int xo = x0 + hq * HB;
+      if (y < y1) {
+        gchar* row = gdst + y * pkb;   // rows differ across the wave
+        if (xo + HB <= wk) {
+          // consecutive dwords: the compiler merges them into one wide store
+#pragma unroll
+          for (int j = 0; j < HB; ++j) store_at(row, (uint32_t)(xo + j) * 4u, acc[j]);
+        } else {
+#pragma unroll
+          for (int j = 0; j < HB; ++j)
+            if (xo + j < wk) store_at(row, (uint32_t)(xo + j) * 4u, acc[j]);
         }
       }
     }
-  };
-
-  // horizontal pass of the staged block into ring slot `slot`
-  const int hr = t % B, hq = t / B;
-  auto hpass = [&](int slot) {
-    const float4* in = reinterpret_cast<const float4*>(&s_in[hr * SS + hq * HB]);
-    float acc[HB];
+    // slide the window by B rows
 #pragma unroll
-    for (int m = 0; m < HB; ++m) acc[m] = 0.0f;
+    for (int i = 0; i < 2 * R; ++i) w[i] = w[i + B];
 #pragma unroll
-    for (int j4 = 0; j4 < NH; ++j4) {
-      const float4 q = in[j4];
-      const float qv[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = 4 * j4 + u;
-#pragma unroll
-        for (int m = 0; m < HB; ++m) {
-          const int tt = j - m;
-          if (tt >= 0 && tt <= 2 * R) acc[m] = __fmaf_rn(a.taps[tt], qv[u], acc[m]);
-        }
-      }
-    }
-    float4* out = reinterpret_cast<float4*>(&s_ring[(slot * B + hr) * RS + hq * HB]);
-#pragma unroll
-    for (int m = 0; m < HB / 4; ++m)
-      out[m] = make_float4(acc[4 * m], acc[4 * m + 1], acc[4 * m + 2], acc[4 * m + 3]);
-  };
-
-  // vertical pass: output rows y0 + mB .. + B - 1 at column x0 + t; H-row
-  // mB + j lives in block m + j / B, i.e. ring slot (m + j / B) % NB
-  const bool col_ok = x0 + t < wk;
-  auto vpass = [&](int m) {
-    const float* base[NB];
-#pragma unroll
-    for (int q = 0; q < NB; ++q) base[q] = &s_ring[((m + q) % NB) * B * RS + t];
-    float acc[B];
-#pragma unroll
-    for (int i = 0; i < B; ++i) acc[i] = 0.0f;
-#pragma unroll
-    for (int j = 0; j < B + 2 * R; ++j) {
-      const float v = base[j / B][(j % B) * RS];
-#pragma unroll
-      for (int i = 0; i < B; ++i) {
-        const int tt = j - i;
-        if (tt >= 0 && tt <= 2 * R) acc[i] = __fmaf_rn(a.taps[tt], v, acc[i]);
-      }
-    }
-    if (col_ok) {
-      const int yb = y0 + m * B;
-      const uint32_t off = (uint32_t)(x0 + t) * 4u;
-#pragma unroll
-      for (int i = 0; i < B; ++i)
-        if (yb + i < y1) store_at(uniform_ptr(gdst + (yb + i) * pkb), off, acc[i]);
-    }
-  };
-
-  // lead-in: blocks 0 .. NB - 2 hold H-rows y0 - R .. y0 - R + (NB - 1) B - 1
-  load_block(0);
-  for (int beta = 0; beta < NB - 1; ++beta) {
-    if (beta > 0) __syncthreads();     // previous horizontal pass done with s_in
-    store_block(beta);
-    __syncthreads();
-    load_block(beta + 1);              // NBLK >= NB, so block beta + 1 exists
-    hpass(beta);
-  }
-  // step m: block m + NB - 1 into slot (m + NB - 1) % NB, then outputs of step m
-  for (int m = 0; m < M; ++m) {
-    const int beta = m + NB - 1;
-    __syncthreads();                   // s_in free; ring slot of block m - 1 free
-    store_block(beta);
-    __syncthreads();
-    if (beta + 1 < NBLK) load_block(beta + 1);
-    hpass(beta % NB);
-    __syncthreads();
-    vpass(m);
+    for (int r = 0; r < B; ++r) w[2 * R + r] = pre[r];
   }
 }
 
@@ -270,7 +243,7 @@ static BlurKernel blur_kernel(int radius, bool up) {
 hipError_t launch_blur(const BlurArgs& a, int radius, int grid, hipStream_t stream) {
   BlurKernel fn = blur_kernel(radius, a.mode == kSrcUpsample);
   if (!fn || a.th % kBlurRows != 0) return hipErrorInvalidValue;
-  return launch(fn, dim3(grid), dim3(kTileW), stream, a);
+  return launch(fn, dim3(grid), dim3(kBlurThreads), stream, a);
 }
 
 }  // namespace sift

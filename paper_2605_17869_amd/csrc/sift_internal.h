@@ -21,7 +21,8 @@ namespace sift {
 constexpr int kMaxOct = 12;        // octaves including octave -1
 constexpr int kMaxScales = 6;      // n_scales supported by the detector
 constexpr int kMaxRadius = 24;     // largest Gaussian radius ceil(4 sigma)
-constexpr int kTileW = 128;        // blur strip width (output columns of one work-group)
+constexpr int kTileW = 192;        // blur strip width (output columns of one work-group)
+constexpr int kBlurThreads = 256;  // blur work-group size (one source column per thread)
 constexpr int kBlurRows = 16;      // rows a blur work-group advances per step
 constexpr int kNumTileH = 4;       // blur chunk heights 64, 128, 256, 512
 constexpr int kXcds = 8;           // work-groups are dealt round-robin to the XCDs
