@@ -21,6 +21,7 @@ namespace sift {
 constexpr int kMaxOct = 12;        // octaves including octave -1
 constexpr int kMaxScales = 6;      // n_scales supported by the detector
 constexpr int kMaxRadius = 24;     // largest Gaussian radius ceil(4 sigma)
+constexpr int kMaxDsp = SIFT_MAX_DSP;  // pooled domain sizes
 constexpr int kTileW = 192;        // blur strip width (output columns of one work-group)
 constexpr int kBlurThreads = 256;  // blur work-group size (one source column per thread)
 constexpr int kBlurRows = 16;      // rows a blur work-group advances per step

@@ -534,17 +534,20 @@ __global__ __launch_bounds__(256) void k_ori_scan(char* ws, HdrPtrs hp, int n, D
 }
 
 // ---------------------------------------------------------------------------
-// Descriptor: one wave per output keypoint.  For each pooled domain size the
-// bounding square of the rotated 4x4 grid is scanned 64 samples at a time;
-// the samples whose rotated cell coordinates fall in (-1, 4) (about 60% of
-// the square) are packed, with their pixel gradients, into full 64-lane
-// batches by a lane permutation in registers, so the trilinear binning runs
-// with every lane busy.  Each lane accumulates into its own LDS column of the
+// Descriptor: one wave per output keypoint.  The bounding square of the
+// rotated 4x4 grid of the largest pooled domain size is scanned 64 samples at
+// a time; the samples whose rotated cell coordinates fall in (-1, 4) (about
+// 60% of the square) are packed, with their pixel gradients, into full
+// 64-lane batches by a lane permutation in registers, so the trilinear
+// binning runs with every lane busy; each packed pixel is binned for every
+// domain size whose window holds it.  Each lane accumulates into its own LDS column of the
 // 128-bin histogram.  Scan, packing and column order are fixed, so the sums
 // are too.  The lane columns are summed in a fixed order, averaged over domain
 // sizes, then L2-normalised, clamped, L2-normalised and optionally turned into
 // RootSIFT (L1 normalise, square root).
 
+// ND: the number of domain sizes the code is unrolled for (1, or the most).
+template <int ND>
 __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, DevParams p) {
   __shared__ float hist[kDescDim * 64];
   const int* kpp = hp.kp_prefix;
@@ -584,44 +587,68 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
 #pragma unroll
     for (int bn = 0; bn < kDescDim; ++bn) hist[bn * 64 + lane] = 0.0f;
 
-    for (int ds = 0; ds < p.n_dsp; ++ds) {
-      const float wc = p.desc_magnif * kp.sigma_oct * p.dsp[ds];
-      const float inv_wc = 1.0f / wc;
-      // A sample contributes only if its rotated cell coordinates fall in
-      // (-1, 4), i.e. |u|, |v| < 2.5 wc (|cos| + |sin|) around the sub-pixel
-      // centre; one extra ring covers the sub-pixel offset and fp32 rounding.
-      const int R = (int)ceilf(2.5f * wc * (fabsf(ct) + fabsf(st))) + 1;
-      const int side = 2 * R + 1;
-      const int nsamp = side * side;
-      const float inv_side = 1.0f / (float)side;
+    // Domain sizes: a pixel inside the window of one size is inside the
+    // window of every larger one (the cell test is monotone in 1 / cell, in
+    // fp32 too), so one scan of the largest window finds every contributing
+    // pixel; its gradient, magnitude and orientation bin are computed once
+    // and its contribution is then added for each size whose window holds it.
+    float smax = p.dsp[0];
+    for (int ds = 1; ds < p.n_dsp; ++ds) smax = fmaxf(smax, p.dsp[ds]);
+    const float wc_max = p.desc_magnif * kp.sigma_oct * smax;
+    const float inv_max = 1.0f / wc_max;
+    // A sample contributes only if its rotated cell coordinates fall in
+    // (-1, 4), i.e. |u|, |v| < 2.5 wc (|cos| + |sin|) around the sub-pixel
+    // centre; one extra ring covers the sub-pixel offset and fp32 rounding.
+    const int R = (int)ceilf(2.5f * wc_max * (fabsf(ct) + fabsf(st))) + 1;
+    const int side = 2 * R + 1;
+    const int nsamp = side * side;
+    const float inv_side = 1.0f / (float)side;
+    // 1 / cell size of every domain size (unused entries 0)
+    float inv_ws[ND];
+#pragma unroll
+    for (int ds = 0; ds < ND; ++ds)
+      inv_ws[ds] = ds < p.n_dsp ? 1.0f / (p.desc_magnif * kp.sigma_oct * p.dsp[ds]) : 0.0f;
 
-      // rotated, cell-scaled coordinates of offset (dx, dy)
-      auto rotate = [&](int dx, int dy, float& xr, float& yr) {
-        const float fu = (float)dx - kp.dx;
-        const float fv = (float)dy - kp.dy;
-        xr = (ct * fu + st * fv) * inv_wc;
-        yr = (ct * fv - st * fu) * inv_wc;
-      };
-      // trilinear binning of one contributing sample into this lane's column
-      auto accumulate = [&](int pxy, float gx, float gy) {
-        const int dx = (int)(short)(pxy & 0xffff), dy = pxy >> 16;
-        float xr, yr;
-        rotate(dx, dy, xr, yr);
+    // rotated offset (dx, dy) from the sub-pixel centre, in pixels
+    auto rotate = [&](int dx, int dy, float& xr0, float& yr0) {
+      const float fu = (float)dx - kp.dx;
+      const float fv = (float)dy - kp.dy;
+      xr0 = ct * fu + st * fv;
+      yr0 = ct * fv - st * fu;
+    };
+    auto in_window = [](float xr, float yr) {
+      const float rb = yr + 1.5f, cb = xr + 1.5f;
+      return rb > -1.0f && rb < 4.0f && cb > -1.0f && cb < 4.0f;
+    };
+    // trilinear binning of one contributing pixel into this lane's column,
+    // once per domain size whose window holds it
+    auto accumulate = [&](int pxy, float gx, float gy) {
+      const int dx = (int)(short)(pxy & 0xffff), dy = pxy >> 16;
+      float xr0, yr0;
+      rotate(dx, dy, xr0, yr0);
+      const float mag = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);
+      float ta = atan2_poly(gy, gx);
+      if (ta < 0.0f) ta += kTwoPi;
+      float ob = ta - th;
+      if (ob < 0.0f) ob += kTwoPi;
+      if (ob >= kTwoPi) ob -= kTwoPi;
+      ob = ob * (8.0f / kTwoPi);
+      const float o0 = floorf(ob);
+      const float fo = ob - o0;
+      int io = (int)o0;
+      if (io >= 8) io -= 8;
+      const int io1 = (io + 1) & 7;
+#pragma unroll
+      for (int ds = 0; ds < ND; ++ds) {
+        if (ds >= p.n_dsp) break;
+        const float xr = xr0 * inv_ws[ds], yr = yr0 * inv_ws[ds];
+        // with one size the scan's window test was this very test
+        if (ND > 1 && !in_window(xr, yr)) continue;
         const float rb = yr + 1.5f, cb = xr + 1.5f;
-        const float mag = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);
-        float ta = atan2_poly(gy, gx);
-        if (ta < 0.0f) ta += kTwoPi;
-        float ob = ta - th;
-        if (ob < 0.0f) ob += kTwoPi;
-        if (ob >= kTwoPi) ob -= kTwoPi;
-        ob = ob * (8.0f / kTwoPi);
         const float wgt = mag * exp_fast(-(xr * xr + yr * yr) * 0.125f);
-        const float r0 = floorf(rb), c0 = floorf(cb), o0 = floorf(ob);
-        const float fr = rb - r0, fc = cb - c0, fo = ob - o0;
+        const float r0 = floorf(rb), c0 = floorf(cb);
+        const float fr = rb - r0, fc = cb - c0;
         const int ir = (int)r0, ic = (int)c0;   // in -1..3
-        int io = (int)o0;
-        if (io >= 8) io -= 8;
-        const int io1 = (io + 1) & 7;
         // The sample spreads over rows ir, ir + 1 (weights 1 - fr, fr) and
         // columns ic, ic + 1 of the 4 x 4 grid, orientations io and io + 1.
         // It updates the 2 x 2 grid cells from (rr0, cc0) = (ir, ic) clamped
@@ -660,69 +687,68 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
             h1[off] = hv[4 * a + 2 * bb + 1] + wv[4 * a + 2 * bb + 1];
           }
         }
-      };
+      }
+    };
 
-      // Pending contributing samples sit in lanes [0, fill): packed offset
-      // (dy << 16 | dx & 0xffff) and gradient.
-      int fill = 0;
-      int p_xy = 0;
-      float p_gx = 0.0f, p_gy = 0.0f;
-      constexpr int U = 4;   // scan batches whose loads are issued together
-      for (int q0 = 0; q0 < nsamp; q0 += 64 * U) {
-        float ga[U], gb[U], gc[U], gd[U];
-        int sxy[U];
-        bool ok[U];
+    // Pending contributing pixels sit in lanes [0, fill): packed offset
+    // (dy << 16 | dx & 0xffff) and gradient.
+    int fill = 0;
+    int p_xy = 0;
+    float p_gx = 0.0f, p_gy = 0.0f;
+    constexpr int U = 4;   // scan batches whose loads are issued together
+    for (int q0 = 0; q0 < nsamp; q0 += 64 * U) {
+      float ga[U], gb[U], gc[U], gd[U];
+      int sxy[U];
+      bool ok[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int qq = q0 + 64 * u + lane;
-          // qq / side through fp32: exact for side < 2048 (the quotient is
-          // at least 0.5 / side away from an integer)
-          const int qy = (int)(((float)qq + 0.5f) * inv_side);
-          const int dy = qy - R, dx = qq - qy * side - R;
-          const int rr = kp.r + dy, cc = kp.c + dx;
-          float xr, yr;
-          rotate(dx, dy, xr, yr);
-          const float rb = yr + 1.5f, cb = xr + 1.5f;
-          ok[u] = qq < nsamp && rr >= 1 && rr <= hk - 2 && cc >= 1 && cc <= wk - 2 &&
-                  rb > -1.0f && rb < 4.0f && cb > -1.0f && cb < 4.0f;
-          sxy[u] = (dy << 16) | (dx & 0xffff);
-          // samples that do not contribute read the (interior) centre instead
-          const uint32_t at = (uint32_t)((ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c)) * 4u;
-          ga[u] = load_at(gL, at + 4u);
-          gb[u] = load_at(gL, at - 4u);
-          gc[u] = load_at(gL, at + pkb);
-          gd[u] = load_at(gL, at - pkb);
-        }
+      for (int u = 0; u < U; ++u) {
+        const int qq = q0 + 64 * u + lane;
+        // qq / side through fp32: exact for side < 2048 (the quotient is
+        // at least 0.5 / side away from an integer)
+        const int qy = (int)(((float)qq + 0.5f) * inv_side);
+        const int dy = qy - R, dx = qq - qy * side - R;
+        const int rr = kp.r + dy, cc = kp.c + dx;
+        float xr0, yr0;
+        rotate(dx, dy, xr0, yr0);
+        ok[u] = qq < nsamp && rr >= 1 && rr <= hk - 2 && cc >= 1 && cc <= wk - 2 &&
+                in_window(xr0 * inv_max, yr0 * inv_max);
+        sxy[u] = (dy << 16) | (dx & 0xffff);
+        // samples that do not contribute read the (interior) centre instead
+        const uint32_t at = (uint32_t)((ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c)) * 4u;
+        ga[u] = load_at(gL, at + 4u);
+        gb[u] = load_at(gL, at - 4u);
+        gc[u] = load_at(gL, at + pkb);
+        gd[u] = load_at(gL, at - pkb);
+      }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint64_t m = __ballot(ok[u]);
-          const int cnt = __popcll(m);
-          const int rank = __popcll(m & lanemask_lt());
-          // contributing lanes go to [fill, fill + cnt), the others after them
-          const int dest = (ok[u] ? fill + rank : fill + cnt + (lane - rank)) & 63;
-          const int r_xy = lane_send(dest, sxy[u]);
-          const float r_gx = lane_send(dest, ga[u] - gb[u]);
-          const float r_gy = lane_send(dest, gc[u] - gd[u]);
-          const int nf = fill + cnt;
-          if (nf >= 64) {
-            // lanes [fill, 64) complete the batch; lanes [0, nf - 64) overflow
-            const bool fresh = lane >= fill;
-            accumulate(fresh ? r_xy : p_xy, fresh ? r_gx : p_gx, fresh ? r_gy : p_gy);
-            p_xy = r_xy;
-            p_gx = r_gx;
-            p_gy = r_gy;
-            fill = nf - 64;
-          } else {
-            const bool take = lane >= fill && lane < nf;
-            p_xy = take ? r_xy : p_xy;
-            p_gx = take ? r_gx : p_gx;
-            p_gy = take ? r_gy : p_gy;
-            fill = nf;
-          }
+      for (int u = 0; u < U; ++u) {
+        const uint64_t m = __ballot(ok[u]);
+        const int cnt = __popcll(m);
+        const int rank = __popcll(m & lanemask_lt());
+        // contributing lanes go to [fill, fill + cnt), the others after them
+        const int dest = (ok[u] ? fill + rank : fill + cnt + (lane - rank)) & 63;
+        const int r_xy = lane_send(dest, sxy[u]);
+        const float r_gx = lane_send(dest, ga[u] - gb[u]);
+        const float r_gy = lane_send(dest, gc[u] - gd[u]);
+        const int nf = fill + cnt;
+        if (nf >= 64) {
+          // lanes [fill, 64) complete the batch; lanes [0, nf - 64) overflow
+          const bool fresh = lane >= fill;
+          accumulate(fresh ? r_xy : p_xy, fresh ? r_gx : p_gx, fresh ? r_gy : p_gy);
+          p_xy = r_xy;
+          p_gx = r_gx;
+          p_gy = r_gy;
+          fill = nf - 64;
+        } else {
+          const bool take = lane >= fill && lane < nf;
+          p_xy = take ? r_xy : p_xy;
+          p_gx = take ? r_gx : p_gx;
+          p_gy = take ? r_gy : p_gy;
+          fill = nf;
         }
       }
-      if (lane < fill) accumulate(p_xy, p_gx, p_gy);
     }
+    if (lane < fill) accumulate(p_xy, p_gx, p_gy);
     wave_lds_sync();
     float h0 = 0.0f, h1 = 0.0f;
     for (int t = 0; t < 64; ++t) {
@@ -825,7 +851,8 @@ hipError_t launch_ori_scan(char* ws, const HdrPtrs& hp, int n, const DevParams& 
 
 hipError_t launch_describe(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
                          hipStream_t stream) {
-  return launch(k_describe, dim3(grid), dim3(64), stream, ws, hp, n, p);
+  if (p.n_dsp == 1) return launch(k_describe<1>, dim3(grid), dim3(64), stream, ws, hp, n, p);
+  return launch(k_describe<kMaxDsp>, dim3(grid), dim3(64), stream, ws, hp, n, p);
 }
 
 }  // namespace sift
