@@ -95,6 +95,17 @@ __device__ __forceinline__ float exp_fast(float x) {
   return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
 }
 
+// Value of lane l - 1 (lane 0 keeps its own) and of lane l + 1 (lane 63
+// keeps its own): whole-wave DPP shifts, no LDS round trip.
+__device__ __forceinline__ float lane_prev(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
+                                                    0x138 /* wave_shr:1 */, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_next(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v),
+                                                    0x130 /* wave_shl:1 */, 0xf, 0xf, false));
+}
+
 // Lanes below this one in the wave.
 __device__ __forceinline__ uint64_t lanemask_lt() {
   return (1ull << (threadIdx.x & 63)) - 1ull;

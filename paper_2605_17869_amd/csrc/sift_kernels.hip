@@ -76,8 +76,8 @@ __device__ __forceinline__ void det_load_row(DetRow<S>& d, const float* const* L
 #pragma unroll
   for (int j = 0; j < S + 2; ++j) {
     const float v = lv[j + 1] - lv[j];
-    const float l = __shfl_up(v, 1, 64);
-    const float r = __shfl_down(v, 1, 64);
+    const float l = lane_prev(v);
+    const float r = lane_next(v);
     d.own[j] = v;
     d.lrmx[j] = fmaxf(l, r);
     d.lrmn[j] = fminf(l, r);
