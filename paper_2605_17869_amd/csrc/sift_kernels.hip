@@ -549,7 +549,9 @@ __global__ __launch_bounds__(256) void k_ori_scan(char* ws, HdrPtrs hp, int n, D
 // ND: the number of domain sizes the code is unrolled for (1, or the most).
 template <int ND>
 __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, DevParams p) {
-  __shared__ float hist[kDescDim * 64];
+  // two lanes per histogram column (lanes l and l + 32), adding in turn
+  constexpr int DC = 32, NG = 64 / DC;
+  __shared__ float hist[kDescDim * DC];
   const int* kpp = hp.kp_prefix;
   const int total = kpp[n];
   const ImgEntry* tab = hp.table;
@@ -585,7 +587,8 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
     const float st = sinf(th), ct = cosf(th);
 
 #pragma unroll
-    for (int bn = 0; bn < kDescDim; ++bn) hist[bn * 64 + lane] = 0.0f;
+    for (int bn = lane; bn < kDescDim * DC; bn += 64) hist[bn] = 0.0f;
+    wave_lds_sync();
 
     // Domain sizes: a pixel inside the window of one size is inside the
     // window of every larger one (the cell test is monotone in 1 / cell, in
@@ -621,8 +624,9 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
       return rb > -1.0f && rb < 4.0f && cb > -1.0f && cb < 4.0f;
     };
     // trilinear binning of one contributing pixel into this lane's column,
-    // once per domain size whose window holds it
-    auto accumulate = [&](int pxy, float gx, float gy) {
+    // once per domain size whose window holds it; every lane of the wave
+    // takes part (lanes with valid == false add nothing)
+    auto accumulate = [&](int pxy, float gx, float gy, bool valid) {
       const int dx = (int)(short)(pxy & 0xffff), dy = pxy >> 16;
       float xr0, yr0;
       rotate(dx, dy, xr0, yr0);
@@ -643,7 +647,7 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
         if (ds >= p.n_dsp) break;
         const float xr = xr0 * inv_ws[ds], yr = yr0 * inv_ws[ds];
         // with one size the scan's window test was this very test
-        if (ND > 1 && !in_window(xr, yr)) continue;
+        const bool add = valid && (ND == 1 || in_window(xr, yr));
         const float rb = yr + 1.5f, cb = xr + 1.5f;
         const float wgt = mag * exp_fast(-(xr * xr + yr * yr) * 0.125f);
         const float r0 = floorf(rb), c0 = floorf(cb);
@@ -663,29 +667,48 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
         const float wc1 = ic == cc0 ? fc : (ic < cc0 ? 0.0f : 1.0f - fc);
         const float wa[2] = {wgt * wr0, wgt * wr1};
         const float wb[2] = {wc0, wc1};
-        float* h0 = &hist[((rr0 * 4 + cc0) * 8 + io) * 64 + lane];
-        float* h1 = &hist[((rr0 * 4 + cc0) * 8 + io1) * 64 + lane];
-        float hv[8], wv[8];
+        // rb, cb of a lane that adds nothing may lie anywhere: keep its
+        // (unused) addresses on the grid
+        const int cb0 = add ? (rr0 * 4 + cc0) * 8 : 0;
+        float* h0 = &hist[(cb0 + io) * DC + (lane & (DC - 1))];
+        float* h1 = &hist[(cb0 + io1) * DC + (lane & (DC - 1))];
+        float wv[8];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
 #pragma unroll
           for (int bb = 0; bb < 2; ++bb) {
-            const int off = (a * 4 + bb) * 8 * 64;   // cell step: 8 bins of 64 lanes
             const float w2 = wa[a] * wb[bb];
             wv[4 * a + 2 * bb] = w2 * (1.0f - fo);
             wv[4 * a + 2 * bb + 1] = w2 * fo;
-            hv[4 * a + 2 * bb] = h0[off];
-            hv[4 * a + 2 * bb + 1] = h1[off];
           }
         }
+        // the lane groups sharing a column update it in turn, each with its
+        // own instructions: read the eight targets, then write them
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
+        for (int grp = 0; grp < NG; ++grp) {
+          if (add && lane / DC == grp) {
+            float hv[8];
 #pragma unroll
-          for (int bb = 0; bb < 2; ++bb) {
-            const int off = (a * 4 + bb) * 8 * 64;
-            h0[off] = hv[4 * a + 2 * bb] + wv[4 * a + 2 * bb];
-            h1[off] = hv[4 * a + 2 * bb + 1] + wv[4 * a + 2 * bb + 1];
+            for (int a = 0; a < 2; ++a) {
+#pragma unroll
+              for (int bb = 0; bb < 2; ++bb) {
+                const int off = (a * 4 + bb) * 8 * DC;   // cell step: 8 bins of DC columns
+                hv[4 * a + 2 * bb] = h0[off];
+                hv[4 * a + 2 * bb + 1] = h1[off];
+              }
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+#pragma unroll
+              for (int bb = 0; bb < 2; ++bb) {
+                const int off = (a * 4 + bb) * 8 * DC;
+                h0[off] = hv[4 * a + 2 * bb] + wv[4 * a + 2 * bb];
+                h1[off] = hv[4 * a + 2 * bb + 1] + wv[4 * a + 2 * bb + 1];
+              }
+            }
           }
+          // keeps the groups' updates in separate instructions, in order
+          __builtin_amdgcn_wave_barrier();
         }
       }
     };
@@ -734,7 +757,7 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
         if (nf >= 64) {
           // lanes [fill, 64) complete the batch; lanes [0, nf - 64) overflow
           const bool fresh = lane >= fill;
-          accumulate(fresh ? r_xy : p_xy, fresh ? r_gx : p_gx, fresh ? r_gy : p_gy);
+          accumulate(fresh ? r_xy : p_xy, fresh ? r_gx : p_gx, fresh ? r_gy : p_gy, true);
           p_xy = r_xy;
           p_gx = r_gx;
           p_gy = r_gy;
@@ -748,13 +771,13 @@ __global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, De
         }
       }
     }
-    if (lane < fill) accumulate(p_xy, p_gx, p_gy);
+    accumulate(p_xy, p_gx, p_gy, lane < fill);
     wave_lds_sync();
     float h0 = 0.0f, h1 = 0.0f;
-    for (int t = 0; t < 64; ++t) {
-      const int col = (lane + t) & 63;
-      h0 += hist[lane * 64 + col];
-      h1 += hist[(lane + 64) * 64 + col];
+    for (int t = 0; t < DC; ++t) {
+      const int col = (lane + t) & (DC - 1);
+      h0 += hist[lane * DC + col];
+      h1 += hist[(lane + 64) * DC + col];
     }
     const float kf = (float)p.n_dsp;
     h0 = h0 / kf;
