@@ -547,10 +547,13 @@ __global__ __launch_bounds__(256) void k_ori_scan(char* ws, HdrPtrs hp, int n, D
 // RootSIFT (L1 normalise, square root).
 
 // ND: the number of domain sizes the code is unrolled for (1, or the most).
+// The bound of 16 resident groups per CU caps registers at 128 per lane.
 template <int ND>
-__global__ __launch_bounds__(64) void k_describe(char* ws, HdrPtrs hp, int n, DevParams p) {
-  // two lanes per histogram column (lanes l and l + 32), adding in turn
-  constexpr int DC = 32, NG = 64 / DC;
+__global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n, DevParams p) {
+  // DC histogram columns: lanes l, l + DC, ... share column l % DC and add
+  // in turn.  Four lanes per column with one domain size; with several, two
+  // (their unrolled size loop needs the registers a third resident wave would)
+  constexpr int DC = ND == 1 ? 16 : 32, NG = 64 / DC;
   __shared__ float hist[kDescDim * DC];
   const int* kpp = hp.kp_prefix;
   const int total = kpp[n];
