@@ -381,7 +381,10 @@ __global__ __launch_bounds__(256) void k_refine(char* ws, HdrPtrs hp, int n, Dev
 // neighbours.
 
 __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, DevParams p) {
-  __shared__ float s_hist[4][kOriBins * 64];
+  // OC histogram columns per wave: lanes l, l + OC, ... share column l % OC
+  // and add in turn (each group with instructions of its own)
+  constexpr int OC = 16, OG = 64 / OC;
+  __shared__ float s_hist[4][kOriBins * OC];
   __shared__ float s_bins[4][kOriBins];
   const int* cp = hp.cand_prefix;
   const int total = cp[n];
@@ -418,17 +421,18 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
     const float inv2 = 1.0f / (2.0f * sw * sw);
     const int side = 2 * R + 1;
     const int nsamp = side * side;
-#pragma unroll
-    for (int bn = 0; bn < kOriBins; ++bn) hist[bn * 64 + lane] = 0.0f;
-    // U samples per lane per pass: their loads are all issued before any is used
+    for (int bn = lane; bn < kOriBins * OC; bn += 64) hist[bn] = 0.0f;
+    wave_lds_sync();
+    // U samples per lane per pass: their loads are all issued before any is
+    // used; the pass count is the same for every lane of the wave
     constexpr int U = 4;
-    for (int q0 = lane; q0 < nsamp; q0 += 64 * U) {
+    for (int q0 = 0; q0 < nsamp; q0 += 64 * U) {
       float ga[U], gb[U], gc[U], gd[U];
       int ddx[U], ddy[U];
       bool ok[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int q = q0 + 64 * u;
+        const int q = q0 + 64 * u + lane;
         const int qy = q / side;
         const int dy = qy - R, dx = q - qy * side - R;
         const int rr = kp.r + dy, cc = kp.c + dx;
@@ -444,7 +448,6 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (!ok[u]) continue;
         const float gx = ga[u] - gb[u];
         const float gy = gc[u] - gd[u];
         const float mag = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);
@@ -458,18 +461,26 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
         if (b0 >= kOriBins) b0 -= kOriBins;
         int b1 = b0 + 1;
         if (b1 >= kOriBins) b1 -= kOriBins;
+        const float w0 = wgt * (1.0f - f), w1 = wgt * f;
         // the two bins differ: read both, then write both
-        float* c0 = &hist[b0 * 64 + lane];
-        float* c1 = &hist[b1 * 64 + lane];
-        const float h0 = *c0, h1 = *c1;
-        *c0 = h0 + wgt * (1.0f - f);
-        *c1 = h1 + wgt * f;
+        float* c0 = &hist[b0 * OC + (lane & (OC - 1))];
+        float* c1 = &hist[b1 * OC + (lane & (OC - 1))];
+#pragma unroll
+        for (int grp = 0; grp < OG; ++grp) {
+          if (ok[u] && lane / OC == grp) {
+            const float h0 = *c0, h1 = *c1;
+            *c0 = h0 + w0;
+            *c1 = h1 + w1;
+          }
+          // keeps the groups' updates in separate instructions, in order
+          __builtin_amdgcn_wave_barrier();
+        }
       }
     }
     wave_lds_sync();
     if (lane < kOriBins) {
       float acc = 0.0f;
-      for (int t = 0; t < 64; ++t) acc += hist[lane * 64 + ((lane + t) & 63)];
+      for (int t = 0; t < OC; ++t) acc += hist[lane * OC + ((lane + t) & (OC - 1))];
       bins[lane] = acc;
     }
     wave_lds_sync();
