@@ -130,11 +130,40 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
     }
   };
   // n consecutive rows from image row ybase (mirrored at the borders)
+  // upsampled rows ybase .. ybase + n - 1 away from the border: the
+  // horizontally interpolated source rows h(j) are loaded once each
+  // (2 loads, not 4 per output row) and combined as fetch() does
+  auto fetch_rows_up = [&](float* dst, int ybase, auto n_c, auto odd_c) {
+    constexpr int n = decltype(n_c)::value;
+    constexpr int odd = decltype(odd_c)::value;   // parity of ybase
+    constexpr int NS = n / 2 + 2;
+    const int s0 = ybase >> 1;
+    float hrow[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const gchar* rp = uniform_ptr(gsrc + min(s0 + i, e.h - 1) * sp);
+      const float va = load_at(rp, ua), vb = load_at(rp, ub);
+      const float top = va - bias;
+      hrow[i] = uo ? (top + (vb - bias)) * 0.5f : top;
+    }
+#pragma unroll
+    for (int r = 0; r < n; ++r) {
+      const int ia = (r + odd) >> 1;          // (ybase + r) / 2 - s0
+      dst[r] = ((r + odd) & 1) ? (hrow[ia] + hrow[ia + 1]) * 0.5f : hrow[ia];
+    }
+  };
   auto fetch_rows = [&](float* dst, int ybase, auto n_c) {
     constexpr int n = decltype(n_c)::value;
     if (ybase >= 0 && ybase + n <= hk) {
+      if (UP) {
+        if (ybase & 1)
+          fetch_rows_up(dst, ybase, n_c, std::integral_constant<int, 1>());
+        else
+          fetch_rows_up(dst, ybase, n_c, std::integral_constant<int, 0>());
+      } else {
 #pragma unroll
-      for (int r = 0; r < n; ++r) dst[r] = fetch(ybase + r);
+        for (int r = 0; r < n; ++r) dst[r] = fetch(ybase + r);
+      }
     } else {
 #pragma unroll
       for (int r = 0; r < n; ++r) dst[r] = fetch(mirror(ybase + r, hk));
