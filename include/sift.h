@@ -83,6 +83,10 @@ typedef struct {
   int32_t tile_rows;          /* 0: library choice; else 64, 128, 256 or 512 rows per blur
                                  work-group.  Any value gives bit-identical results (tuning
                                  only) */
+  int32_t n_streams;          /* 0: library choice (a batch of 8 or more images runs as 4
+                                 sub-batches on the handle's own streams, concurrently);
+                                 1..8: that many sub-batches.  Any value gives bit-identical
+                                 results (tuning only) */
 } sift_params;
 
 /* One keypoint, 48 bytes.  Keypoints of an image come in canonical order:

@@ -84,9 +84,14 @@ void set_last_error(const std::string& msg) { g_error = msg; }
 void set_capturing(bool on) { g_capturing = on; }
 }  // namespace sift
 
+constexpr int kMaxParts = 8;        // sub-batches one batched call may run concurrently
+
 struct sift_handle {
   sift_params params;
   DevParams dev;
+  hipStream_t part_stream[kMaxParts] = {};   // created by the first split batch
+  std::once_flag streams_once;
+  hipError_t streams_status = hipSuccess;
   Taps init;                       // first level of the first octave
   Taps inc[kMaxScales + 2];        // level i from level i-1, i = 1..s+2
 };
@@ -128,6 +133,8 @@ sift_status validate_params(const sift_params& p) {
   if (p.tile_rows != 0 && p.tile_rows != 64 && p.tile_rows != 128 && p.tile_rows != 256 &&
       p.tile_rows != 512)
     return fail(SIFT_ERR_INVALID_ARG, "tile_rows must be 0, 64, 128, 256 or 512");
+  if (p.n_streams < 0 || p.n_streams > kMaxParts)
+    return fail(SIFT_ERR_INVALID_ARG, "n_streams must be in 0..%d", kMaxParts);
   return SIFT_OK;
 }
 
@@ -211,6 +218,46 @@ void prof_end(int rec, hipStream_t stream) {
   hipEventRecord(g_prof.recs[rec].b, stream);
 }
 
+
+// Sub-batches of one batched call: contiguous index ranges of about equal
+// workspace footprint.  With several, they run on the handle's streams
+// concurrently (one image's arithmetic never depends on the others).
+int batch_parts(int32_t n, int parts_wanted, int* first) {
+  int parts = parts_wanted;
+  if (parts < 1) parts = n >= 8 ? 4 : 1;
+  parts = std::min(std::min(parts, kMaxParts), (int)n);
+  first[0] = 0;
+  first[parts] = n;
+  if (parts == 1) return 1;
+  return parts;
+}
+
+void split_parts(const sift_handle* h, int32_t n, const int32_t* heights, const int32_t* widths,
+                 int parts, int* first) {
+  int64_t total = 0;
+  std::vector<int64_t> rb(n);
+  for (int i = 0; i < n; ++i) total += (rb[i] = region_bytes(h, heights[i], widths[i]));
+  int64_t acc = 0;
+  int p = 1;
+  for (int i = 0; i < n && p < parts; ++i) {
+    acc += rb[i];
+    // cut after image i once the running footprint reaches p / parts of the
+    // total, leaving at least one image for each remaining part
+    if (acc * parts >= total * p && n - (i + 1) >= parts - p) first[p++] = i + 1;
+  }
+  while (p < parts) { first[p] = first[p - 1] + 1; ++p; }   // degenerate footprints
+  first[parts] = n;
+}
+
+int64_t part_bytes(const sift_handle* h, int lo, int hi, const int32_t* heights,
+                   const int32_t* widths) {
+  Header hd;
+  make_header(hi - lo, &hd);
+  int64_t b = hd.bytes;
+  for (int i = lo; i < hi; ++i) b += region_bytes(h, heights[i], widths[i]);
+  return b;
+}
+
 }  // namespace
 
 extern "C" {
@@ -291,7 +338,12 @@ sift_status sift_create(const sift_params* p, sift_handle** out) {
   return SIFT_OK;
 }
 
-void sift_destroy(sift_handle* h) { delete h; }
+void sift_destroy(sift_handle* h) {
+  if (!h) return;
+  for (int i = 0; i < kMaxParts; ++i)
+    if (h->part_stream[i]) hipStreamDestroy(h->part_stream[i]);
+  delete h;
+}
 
 sift_status sift_get_params(const sift_handle* h, sift_params* p) {
   if (!h || !p) return fail(SIFT_ERR_INVALID_ARG, "null argument");
@@ -304,15 +356,21 @@ sift_status sift_batch_workspace_size(const sift_handle* h, int32_t n, const int
   if (!h || !heights || !widths || !bytes) return fail(SIFT_ERR_INVALID_ARG, "null argument");
   if (n < 1) return fail(SIFT_ERR_INVALID_ARG, "batch size must be >= 1");
   if (n > kMaxBatch) return fail(SIFT_ERR_TOO_LARGE, "batch above %d images", kMaxBatch);
-  Header hd;
-  make_header(n, &hd);
-  int64_t total = hd.bytes;
   for (int i = 0; i < n; ++i) {
     sift_status st = validate_size(h, heights[i], widths[i]);
     if (st != SIFT_OK) return st;
-    total += region_bytes(h, heights[i], widths[i]);
   }
-  *bytes = (size_t)total;
+  // the sub-batches' layouts one after another (covers the one-part layout)
+  int first[kMaxParts + 1];
+  const int parts = batch_parts(n, h->params.n_streams, first);
+  if (parts > 1) split_parts(h, n, heights, widths, parts, first);
+  int64_t total = 0;
+  for (int q = 0; q < parts; ++q) total += part_bytes(h, first[q], first[q + 1], heights, widths);
+  Header hd;
+  make_header(n, &hd);
+  int64_t one = hd.bytes;
+  for (int i = 0; i < n; ++i) one += region_bytes(h, heights[i], widths[i]);
+  *bytes = (size_t)std::max(total, one);
   return SIFT_OK;
 }
 
@@ -320,29 +378,15 @@ sift_status sift_workspace_size(const sift_handle* h, int32_t height, int32_t wi
   return sift_batch_workspace_size(h, 1, &height, &width, bytes);
 }
 
-sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_images,
-                               const int32_t* heights, const int32_t* widths,
-                               const int64_t* pitches, void* d_workspace,
-                               size_t workspace_bytes, const sift_output* outs, void* stream_v) {
-  if (!h || !d_images || !heights || !widths || !pitches || !d_workspace || !outs)
-    return fail(SIFT_ERR_INVALID_ARG, "null argument");
-  if (n < 1) return fail(SIFT_ERR_INVALID_ARG, "batch size must be >= 1");
-  if (n > kMaxBatch) return fail(SIFT_ERR_TOO_LARGE, "batch above %d images", kMaxBatch);
-  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
-    return fail(SIFT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  for (int i = 0; i < n; ++i) {
-    if (!d_images[i]) return fail(SIFT_ERR_INVALID_ARG, "image %d is null", i);
-    if (pitches[i] < widths[i]) return fail(SIFT_ERR_INVALID_ARG, "image %d: pitch < width", i);
-    if (!outs[i].keypoints || !outs[i].descriptors || !outs[i].count)
-      return fail(SIFT_ERR_INVALID_ARG, "image %d: null output pointer", i);
-    if (outs[i].capacity < 0) return fail(SIFT_ERR_INVALID_ARG, "image %d: negative capacity", i);
-  }
-  size_t need = 0;
-  sift_status st = sift_batch_workspace_size(h, n, heights, widths, &need);
-  if (st != SIFT_OK) return st;
-  if (workspace_bytes < need)
-    return fail(SIFT_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
+}  // extern "C"
 
+namespace {
+
+// The launch sequence of one (sub-)batch on `stream`; arguments already checked.
+sift_status launch_batch(sift_handle* h, int32_t n, const float* const* d_images,
+                         const int32_t* heights, const int32_t* widths, const int64_t* pitches,
+                         void* d_workspace, const sift_output* outs, void* stream_v) {
+  sift_status st = SIFT_OK;
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
   char* ws = static_cast<char*>(d_workspace);
   const DevParams& p = h->dev;
@@ -461,6 +505,77 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
   prof_end(prec, stream);
   return SIFT_OK;
 }
+
+
+}  // namespace
+
+extern "C" {
+
+sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_images,
+                               const int32_t* heights, const int32_t* widths,
+                               const int64_t* pitches, void* d_workspace,
+                               size_t workspace_bytes, const sift_output* outs, void* stream_v) {
+  if (!h || !d_images || !heights || !widths || !pitches || !d_workspace || !outs)
+    return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  if (n < 1) return fail(SIFT_ERR_INVALID_ARG, "batch size must be >= 1");
+  if (n > kMaxBatch) return fail(SIFT_ERR_TOO_LARGE, "batch above %d images", kMaxBatch);
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+    return fail(SIFT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  for (int i = 0; i < n; ++i) {
+    if (!d_images[i]) return fail(SIFT_ERR_INVALID_ARG, "image %d is null", i);
+    if (pitches[i] < widths[i]) return fail(SIFT_ERR_INVALID_ARG, "image %d: pitch < width", i);
+    if (!outs[i].keypoints || !outs[i].descriptors || !outs[i].count)
+      return fail(SIFT_ERR_INVALID_ARG, "image %d: null output pointer", i);
+    if (outs[i].capacity < 0) return fail(SIFT_ERR_INVALID_ARG, "image %d: negative capacity", i);
+  }
+  size_t need = 0;
+  sift_status st = sift_batch_workspace_size(h, n, heights, widths, &need);
+  if (st != SIFT_OK) return st;
+  if (workspace_bytes < need)
+    return fail(SIFT_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
+
+  int first[kMaxParts + 1];
+  int parts = batch_parts(n, h->params.n_streams, first);
+  {
+    // stage profiling times one sequence of launches on the caller's stream
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    if (g_prof.on && !g_capturing) parts = 1;
+  }
+  if (parts == 1)
+    return launch_batch(h, n, d_images, heights, widths, pitches, d_workspace, outs, stream_v);
+  split_parts(h, n, heights, widths, parts, first);
+  std::call_once(h->streams_once, [h] {
+    for (int i = 0; i < kMaxParts && h->streams_status == hipSuccess; ++i)
+      h->streams_status = hipStreamCreateWithFlags(&h->part_stream[i], hipStreamNonBlocking);
+  });
+  if (h->streams_status != hipSuccess) return check_hip(h->streams_status, "sub-batch streams");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+  hipEvent_t ev[kMaxParts + 1] = {};
+  hipError_t e = hipSuccess;
+  for (int q = 0; q <= parts && e == hipSuccess; ++q)
+    e = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming);
+  // fork: every sub-batch stream waits for the caller's stream
+  if (e == hipSuccess) e = hipEventRecord(ev[parts], stream);
+  for (int q = 0; q < parts && e == hipSuccess; ++q)
+    e = hipStreamWaitEvent(h->part_stream[q], ev[parts], 0);
+  char* ws = static_cast<char*>(d_workspace);
+  int64_t off = 0;
+  for (int q = 0; q < parts && e == hipSuccess && st == SIFT_OK; ++q) {
+    const int lo = first[q], hi = first[q + 1];
+    st = launch_batch(h, hi - lo, d_images + lo, heights + lo, widths + lo, pitches + lo,
+                      ws + off, outs + lo, h->part_stream[q]);
+    off += part_bytes(h, lo, hi, heights, widths);
+    if (st == SIFT_OK) e = hipEventRecord(ev[q], h->part_stream[q]);
+  }
+  // join: the caller's stream waits for every sub-batch
+  for (int q = 0; q < parts && e == hipSuccess && st == SIFT_OK; ++q)
+    e = hipStreamWaitEvent(stream, ev[q], 0);
+  for (int q = 0; q <= parts; ++q)
+    if (ev[q]) hipEventDestroy(ev[q]);
+  if (st != SIFT_OK) return st;
+  return check_hip(e, "sub-batch streams");
+}
+
 
 sift_status sift_extract(sift_handle* h, const float* d_image, int32_t height, int32_t width,
                          int64_t pitch, void* d_workspace, size_t workspace_bytes,

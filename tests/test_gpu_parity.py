@@ -204,3 +204,20 @@ def test_tile_rows_do_not_change_results():
         if ref is None:
             ref = got
         assert got == ref, f"tile_rows={rows}"
+
+
+def test_sub_batches_on_streams_are_bitwise_identical():
+    # A batch may run as sub-batches on the handle's streams; every split gives
+    # the bits of extracting each image alone.
+    from paper_2605_17869_amd import Extractor
+    sizes = [(97 + 13 * k, 129 + 7 * ((5 * k) % 11)) for k in range(11)]
+    imgs = [blobs(500 + k, h, w, 3 * DENSITY) for k, (h, w) in enumerate(sizes)]
+    settings = dict(synth.BASE_SETTINGS, n_octaves=2)
+    singles = [extract(Extractor(settings), im) for im in imgs]
+    for streams in (0, 1, 3, 8):
+        say(f"n_streams={streams}")
+        got = extract_batch(Extractor(dict(settings, n_streams=streams)), imgs)
+        for k in range(len(imgs)):
+            a, b = singles[k], got[k]
+            assert digest(a[0], a[1]) == digest(b[0], b[1]), (streams, k)
+            assert a[2:] == b[2:], (streams, k)
