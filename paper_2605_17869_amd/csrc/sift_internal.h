@@ -27,7 +27,8 @@ constexpr int kBlurThreads = 256;  // blur work-group size (one source column pe
 constexpr int kBlurRows = 16;      // rows a blur work-group advances per step
 constexpr int kNumTileH = 4;       // blur chunk heights 64, 128, 256, 512
 constexpr int kXcds = 8;           // work-groups are dealt round-robin to the XCDs
-constexpr int kBand = 16;          // rows per detection band
+constexpr int kBand = 8;           // rows per detection band
+constexpr int kDetectWaves = 4;    // waves of a detection work-group
 constexpr int kSeg = 62;           // output columns per 64-lane detection segment
 constexpr int kOriBins = 36;
 constexpr int kMaxPeaks = kOriBins / 2;   // strict circular maxima of 36 bins

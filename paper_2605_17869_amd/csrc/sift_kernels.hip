@@ -55,9 +55,11 @@ __global__ void k_finalize(HdrPtrs hp, int n, DevParams p) {
 }
 
 // ---------------------------------------------------------------------------
-// Detection.  One work-group per (image, octave, band of kBand rows); each
-// wave walks 64-lane column segments (lanes 1..62 are outputs, lanes 0 and 63
-// their halo) down the band with a 3-row register window of the DoG layers
+// Detection.  One work-group per (image, octave, band of kBand = 8 rows): short
+// bands keep each wave's dependent row loop short, which matters more here
+// than the 2 halo rows a band re-reads.  Each wave walks 64-lane column
+// segments (lanes 1..62 are outputs, lanes 0 and 63 their halo) down the band
+// with a 3-row register window of the DoG layers
 // D_j = L_{j+1} - L_j.  A pixel of layer i is a candidate when |D| exceeds the
 // pre-gate and D is strictly above (below) the maximum (minimum) of its 26
 // neighbours.  The per-row result is a 64-bit ballot word stored per
@@ -87,8 +89,9 @@ __device__ __forceinline__ void det_load_row(DetRow<S>& d, const float* const* L
 }
 
 template <int S>
-__global__ __launch_bounds__(256) void k_detect(char* ws, HdrPtrs hp, int n, DevParams p) {
-  __shared__ int s_cnt[4][S];
+__global__ __launch_bounds__(kDetectWaves * 64) void k_detect(char* ws, HdrPtrs hp, int n,
+                                                             DevParams p) {
+  __shared__ int s_cnt[kDetectWaves][S];
   const int* bp = hp.band_prefix;
   const int item = blockIdx.x;
   const int img = find_owner(bp, n, item);
@@ -113,7 +116,7 @@ __global__ __launch_bounds__(256) void k_detect(char* ws, HdrPtrs hp, int n, Dev
 #pragma unroll
   for (int i = 0; i < S; ++i) cnt[i] = 0;
 
-  for (int sg = wave; sg < nseg; sg += 4) {
+  for (int sg = wave; sg < nseg; sg += kDetectWaves) {
     const int c = b + sg * kSeg + lane - 1;
     const int cl = min(c, wk - 1);
     const bool out_col = lane >= 1 && lane <= kSeg && c < wk - b;
@@ -151,7 +154,9 @@ __global__ __launch_bounds__(256) void k_detect(char* ws, HdrPtrs hp, int n, Dev
   __syncthreads();
   if (threadIdx.x < S) {
     const int i = threadIdx.x;
-    const int tot = s_cnt[0][i] + s_cnt[1][i] + s_cnt[2][i] + s_cnt[3][i];
+    int tot = 0;
+#pragma unroll
+    for (int wv = 0; wv < kDetectWaves; ++wv) tot += s_cnt[wv][i];
     int* bc = reinterpret_cast<int*>(ws + e.region + region_tail(e.h, e.w, lc).band_cnt);
     bc[ov.band_base * S + i * ov.nband + band] = tot;
   }
@@ -846,12 +851,12 @@ hipError_t launch_finalize(const HdrPtrs& hp, int n, const DevParams& p, hipStre
 hipError_t launch_detect(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
                          hipStream_t stream) {
   switch (p.s) {
-    case 1: return launch(k_detect<1>, dim3(grid), dim3(256), stream, ws, hp, n, p);
-    case 2: return launch(k_detect<2>, dim3(grid), dim3(256), stream, ws, hp, n, p);
-    case 3: return launch(k_detect<3>, dim3(grid), dim3(256), stream, ws, hp, n, p);
-    case 4: return launch(k_detect<4>, dim3(grid), dim3(256), stream, ws, hp, n, p);
-    case 5: return launch(k_detect<5>, dim3(grid), dim3(256), stream, ws, hp, n, p);
-    case 6: return launch(k_detect<6>, dim3(grid), dim3(256), stream, ws, hp, n, p);
+    case 1: return launch(k_detect<1>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
+    case 2: return launch(k_detect<2>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
+    case 3: return launch(k_detect<3>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
+    case 4: return launch(k_detect<4>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
+    case 5: return launch(k_detect<5>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
+    case 6: return launch(k_detect<6>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
     default: return hipErrorInvalidValue;
   }
 }
