@@ -893,7 +893,11 @@ hipError_t launch_ori_scan(char* ws, const HdrPtrs& hp, int n, const DevParams& 
 
 hipError_t launch_describe(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
                          hipStream_t stream) {
+  // the smallest unrolled size count that covers n_dsp (5: the paper's
+  // pooling set, 10: the linearly spaced set of its benchmark)
   if (p.n_dsp == 1) return launch(k_describe<1>, dim3(grid), dim3(64), stream, ws, hp, n, p);
+  if (p.n_dsp <= 5) return launch(k_describe<5>, dim3(grid), dim3(64), stream, ws, hp, n, p);
+  if (p.n_dsp <= 10) return launch(k_describe<10>, dim3(grid), dim3(64), stream, ws, hp, n, p);
   return launch(k_describe<kMaxDsp>, dim3(grid), dim3(64), stream, ws, hp, n, p);
 }
 

@@ -95,6 +95,9 @@ CASES = [
      dict(n_octaves=3, dsp_scales=(0.5, 1 / math.sqrt(2), 1.0, math.sqrt(2), 2.0), rootsift=1)),
     ("160x220 K=10 DSP + RootSIFT", 160, 220, dict(n_octaves=3, dsp_scales=synth.dsp_linspace(),
                                                    rootsift=1)),
+    ("150x190 16 DSP sizes, unordered", 150, 190,
+     dict(n_octaves=3, dsp_scales=tuple(1.25 - 0.07 * ((5 * k) % 16) for k in range(16)))),
+    ("140x160 3 DSP sizes", 140, 160, dict(n_octaves=3, dsp_scales=(1.0, 0.6, 1.3))),
     ("120x140 s=2", 120, 140, dict(n_octaves=3, n_scales=2)),
     ("180x200 s=4", 180, 200, dict(n_octaves=3, n_scales=4)),
     ("104x104 minimum size, 4 octaves", 104, 104, dict(n_octaves=4)),
