@@ -321,7 +321,10 @@ sift_status sift_create(const sift_params* p, sift_handle** out) {
   d.ori_peak_ratio = p->ori_peak_ratio;
   d.desc_magnif = p->desc_magnif;
   d.desc_clamp = p->desc_clamp;
+  // largest domain size first: the descriptor kernel stops its size loop at
+  // the first size whose window holds none of a batch's pixels
   for (int i = 0; i < p->n_dsp; ++i) d.dsp[i] = p->dsp_scales[i];
+  std::sort(d.dsp, d.dsp + p->n_dsp, [](float a, float b) { return a > b; });
   // level sigmas: level i of an octave carries sigma0 * k^i, k = 2^(1/s)
   const double s0 = p->sigma0;
   const double assumed = (double)p->sigma_in * (p->upsample ? 2.0 : 1.0);

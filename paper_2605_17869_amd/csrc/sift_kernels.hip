@@ -614,8 +614,8 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
     // fp32 too), so one scan of the largest window finds every contributing
     // pixel; its gradient, magnitude and orientation bin are computed once
     // and its contribution is then added for each size whose window holds it.
-    float smax = p.dsp[0];
-    for (int ds = 1; ds < p.n_dsp; ++ds) smax = fmaxf(smax, p.dsp[ds]);
+    // the sizes come sorted, largest first
+    const float smax = p.dsp[0];
     const float wc_max = p.desc_magnif * kp.sigma_oct * smax;
     const float inv_max = 1.0f / wc_max;
     // A sample contributes only if its rotated cell coordinates fall in
@@ -625,11 +625,15 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
     const int side = 2 * R + 1;
     const int nsamp = side * side;
     const float inv_side = 1.0f / (float)side;
-    // 1 / cell size of every domain size (unused entries 0)
-    float inv_ws[ND];
+    // 1 / cell size of every domain size, and the factor that turns a
+    // squared pixel distance into the base-2 exponent of the grid's Gaussian
+    // weight exp(-(xr^2 + yr^2) / 8) for that size (unused entries 0)
+    float inv_ws[ND], gk_ws[ND];
 #pragma unroll
-    for (int ds = 0; ds < ND; ++ds)
+    for (int ds = 0; ds < ND; ++ds) {
       inv_ws[ds] = ds < p.n_dsp ? 1.0f / (p.desc_magnif * kp.sigma_oct * p.dsp[ds]) : 0.0f;
+      gk_ws[ds] = inv_ws[ds] * inv_ws[ds] * (-0.125f * 1.44269504088896341f);
+    }
 
     // rotated offset (dx, dy) from the sub-pixel centre, in pixels
     auto rotate = [&](int dx, int dy, float& xr0, float& yr0) {
@@ -638,10 +642,9 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
       xr0 = ct * fu + st * fv;
       yr0 = ct * fv - st * fu;
     };
-    auto in_window = [](float xr, float yr) {
-      const float rb = yr + 1.5f, cb = xr + 1.5f;
-      return rb > -1.0f && rb < 4.0f && cb > -1.0f && cb < 4.0f;
-    };
+    // rotated cell coordinates (xr, yr) relative to the grid centre: inside
+    // (-1, 4) after the shift by 1.5, i.e. both below 2.5 in magnitude
+    auto in_window = [](float xr, float yr) { return fmaxf(fabsf(xr), fabsf(yr)) < 2.5f; };
     // trilinear binning of one contributing pixel into this lane's column,
     // once per domain size whose window holds it; every lane of the wave
     // takes part (lanes with valid == false add nothing)
@@ -649,6 +652,7 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
       const int dx = (int)(short)(pxy & 0xffff), dy = pxy >> 16;
       float xr0, yr0;
       rotate(dx, dy, xr0, yr0);
+      const float r2 = xr0 * xr0 + yr0 * yr0;
       const float mag = __builtin_amdgcn_sqrtf(gx * gx + gy * gy);
       float ta = atan2_poly(gy, gx);
       if (ta < 0.0f) ta += kTwoPi;
@@ -661,44 +665,42 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
       int io = (int)o0;
       if (io >= 8) io -= 8;
       const int io1 = (io + 1) & 7;
+      const int col = lane & (DC - 1);
 #pragma unroll
       for (int ds = 0; ds < ND; ++ds) {
         if (ds >= p.n_dsp) break;
         const float xr = xr0 * inv_ws[ds], yr = yr0 * inv_ws[ds];
         // with one size the scan's window test was this very test
         const bool add = valid && (ND == 1 || in_window(xr, yr));
+        // sizes run largest first, and a pixel outside one size's window is
+        // outside every smaller one's: once no lane adds, none will again
+        if (ND > 1 && __ballot(add) == 0ull) break;
+        const float wgt = mag * __builtin_amdgcn_exp2f(r2 * gk_ws[ds]);
+        // The sample updates the 2 x 2 grid cells from (floor(rb), floor(cb))
+        // clamped to 0..2, so the eight targets are always on the grid and
+        // distinct.  A cell at distance d (in cells) from the sample along an
+        // axis gets weight max(0, 1 - |d|): the bilinear weight for the two
+        // cells the sample reaches, +0 for a block row or column it does not
+        // reach (adding +0 to a non-negative sum leaves it unchanged).
         const float rb = yr + 1.5f, cb = xr + 1.5f;
-        const float wgt = mag * exp_fast(-(xr * xr + yr * yr) * 0.125f);
-        const float r0 = floorf(rb), c0 = floorf(cb);
-        const float fr = rb - r0, fc = cb - c0;
-        const int ir = (int)r0, ic = (int)c0;   // in -1..3
-        // The sample spreads over rows ir, ir + 1 (weights 1 - fr, fr) and
-        // columns ic, ic + 1 of the 4 x 4 grid, orientations io and io + 1.
-        // It updates the 2 x 2 grid cells from (rr0, cc0) = (ir, ic) clamped
-        // to 0..2, so the eight targets are always on the grid and distinct:
-        // a target row or column the sample does not reach gets weight +0,
-        // and adding +0 to a non-negative sum leaves it unchanged.  The
-        // eight targets are read first, then written.
-        const int rr0 = min(max(ir, 0), 2), cc0 = min(max(ic, 0), 2);
-        const float wr0 = ir == rr0 ? 1.0f - fr : (ir < rr0 ? fr : 0.0f);
-        const float wr1 = ir == rr0 ? fr : (ir < rr0 ? 0.0f : 1.0f - fr);
-        const float wc0 = ic == cc0 ? 1.0f - fc : (ic < cc0 ? fc : 0.0f);
-        const float wc1 = ic == cc0 ? fc : (ic < cc0 ? 0.0f : 1.0f - fc);
-        const float wa[2] = {wgt * wr0, wgt * wr1};
-        const float wb[2] = {wc0, wc1};
-        // rb, cb of a lane that adds nothing may lie anywhere: keep its
-        // (unused) addresses on the grid
-        const int cb0 = add ? (rr0 * 4 + cc0) * 8 : 0;
-        float* h0 = &hist[(cb0 + io) * DC + (lane & (DC - 1))];
-        float* h1 = &hist[(cb0 + io1) * DC + (lane & (DC - 1))];
+        const float r0 = __builtin_amdgcn_fmed3f(floorf(rb), 0.0f, 2.0f);
+        const float c0 = __builtin_amdgcn_fmed3f(floorf(cb), 0.0f, 2.0f);
+        const float dr = rb - r0, dc = cb - c0;
+        const float wr[2] = {fmaxf(1.0f - fabsf(dr), 0.0f), fmaxf(1.0f - fabsf(dr - 1.0f), 0.0f)};
+        const float wc[2] = {fmaxf(1.0f - fabsf(dc), 0.0f), fmaxf(1.0f - fabsf(dc - 1.0f), 0.0f)};
+        const float wo[2] = {wgt * (1.0f - fo), wgt * fo};
+        // a lane that adds nothing keeps its (unused) addresses on the grid
+        const int cell = add ? (int)(r0 * 4.0f + c0) : 0;
+        float* h0 = &hist[(cell * 8 + io) * DC + col];
+        float* h1 = &hist[(cell * 8 + io1) * DC + col];
         float wv[8];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
+          const float ra0 = wr[a] * wo[0], ra1 = wr[a] * wo[1];
 #pragma unroll
           for (int bb = 0; bb < 2; ++bb) {
-            const float w2 = wa[a] * wb[bb];
-            wv[4 * a + 2 * bb] = w2 * (1.0f - fo);
-            wv[4 * a + 2 * bb + 1] = w2 * fo;
+            wv[4 * a + 2 * bb] = ra0 * wc[bb];
+            wv[4 * a + 2 * bb + 1] = ra1 * wc[bb];
           }
         }
         // the lane groups sharing a column update it in turn, each with its
