@@ -80,9 +80,10 @@ typedef struct {
   int32_t rootsift;           /* 0: 1 applies L1 normalisation then sqrt */
   int32_t max_keypoints;      /* 65536: keypoints kept per image (canonical order) */
   int32_t max_candidates;     /* 65536: detections refined per image (canonical order) */
-  int32_t tile_rows;          /* 0: library choice; else 64, 128, 256 or 512 rows per blur
-                                 work-group.  Any value gives bit-identical results (tuning
-                                 only) */
+  int32_t tile_rows;          /* 0: library choice; else 32, 64, 128, 256 or 512: the most
+                                 rows per blur work-group (octaves too small to give enough
+                                 work-groups at that height use shorter chunks).  Any value
+                                 gives bit-identical results (tuning only) */
   int32_t n_streams;          /* 0: library choice (a batch of 8 or more images runs as 4
                                  sub-batches on the handle's own streams, concurrently);
                                  1..8: that many sub-batches.  Any value gives bit-identical
@@ -217,8 +218,8 @@ sift_status sift_graph_destroy(sift_graph* g);
 
 /*
  * Tuning.  sift_autotune_batch times sift_extract_batch on the given batch
- * for every blur chunk height (64, 128, 256, 512 rows; all give bit-identical
- * results) and returns the fastest in *best_tile_rows and the mean time of
+ * for every cap on the blur chunk height (64, 128, 256, 512 rows; all give
+ * bit-identical results) and returns the fastest in *best_tile_rows and the mean time of
  * each candidate, in that order, in ms[4] (host, may be NULL).  It runs
  * `warmup` untimed and `reps` timed extractions per candidate on `stream` and
  * waits for them (it synchronises; it is not for a capture or a hot loop).

@@ -39,17 +39,18 @@ sift_status fail(sift_status st, const char* fmt, ...) {
 constexpr int kMaxSide = 32768;    // per input dimension
 constexpr int kMaxBatch = 4096;
 
-// Chunk height class of a blur level: the caller's choice, else the tallest
-// chunk that still gives at least kBlurTargetGroups work-groups (enough to
-// fill every CU several times over), else the shortest.
+// Chunk height class of a blur level: the tallest chunk, up to the caller's
+// tile_rows when set, that still gives at least kBlurTargetGroups work-groups
+// (enough to fill every CU several times over), else the shortest.  Small
+// octaves so get short chunks whatever the cap: more work-groups, shorter
+// row loops.
 constexpr int kBlurTargetGroups = 2048;
 
 int blur_class(int tile_rows, const int64_t* tiles_of_class) {
-  if (tile_rows) {
-    for (int c = 0; c < kNumTileH; ++c)
-      if (tile_h_of(c) == tile_rows) return c;
-  }
-  for (int c = kNumTileH - 1; c > 0; --c)
+  int top = kNumTileH - 1;
+  for (int c = 0; c < kNumTileH; ++c)
+    if (tile_h_of(c) == tile_rows) top = c;
+  for (int c = top; c > 0; --c)
     if (tiles_of_class[c] >= kBlurTargetGroups) return c;
   return 0;
 }
@@ -130,9 +131,9 @@ sift_status validate_params(const sift_params& p) {
   if (p.max_keypoints < 0) return fail(SIFT_ERR_INVALID_ARG, "max_keypoints must be >= 0");
   if (p.max_candidates < 1 || p.max_candidates > (1 << 24))
     return fail(SIFT_ERR_INVALID_ARG, "max_candidates must be in 1..2^24");
-  if (p.tile_rows != 0 && p.tile_rows != 64 && p.tile_rows != 128 && p.tile_rows != 256 &&
-      p.tile_rows != 512)
-    return fail(SIFT_ERR_INVALID_ARG, "tile_rows must be 0, 64, 128, 256 or 512");
+  if (p.tile_rows != 0 && p.tile_rows != 32 && p.tile_rows != 64 && p.tile_rows != 128 &&
+      p.tile_rows != 256 && p.tile_rows != 512)
+    return fail(SIFT_ERR_INVALID_ARG, "tile_rows must be 0, 32, 64, 128, 256 or 512");
   if (p.n_streams < 0 || p.n_streams > kMaxParts)
     return fail(SIFT_ERR_INVALID_ARG, "n_streams must be in 0..%d", kMaxParts);
   return SIFT_OK;

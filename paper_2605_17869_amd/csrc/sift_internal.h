@@ -25,7 +25,7 @@ constexpr int kMaxDsp = SIFT_MAX_DSP;  // pooled domain sizes
 constexpr int kTileW = 192;        // blur strip width (output columns of one work-group)
 constexpr int kBlurThreads = 256;  // blur work-group size (one source column per thread)
 constexpr int kBlurRows = 16;      // rows a blur work-group advances per step
-constexpr int kNumTileH = 4;       // blur chunk heights 64, 128, 256, 512
+constexpr int kNumTileH = 5;       // blur chunk heights 32, 64, 128, 256, 512
 constexpr int kXcds = 8;           // work-groups are dealt round-robin to the XCDs
 constexpr int kBand = 8;           // rows per detection band
 constexpr int kDetectWaves = 4;    // waves of a detection work-group
@@ -193,7 +193,7 @@ struct ImgEntry {
 };
 
 // Workspace header: image table and per-octave tile prefix sums.
-SIFT_HD int tile_h_of(int cls) { return 64 << cls; }
+SIFT_HD int tile_h_of(int cls) { return 32 << cls; }
 
 struct Header {
   int64_t table;           // ImgEntry[n]

@@ -25,6 +25,9 @@ __global__ void k_setup(HdrPtrs hp, SetupChunk c) {
   if (t < c.count) const_cast<ImgEntry*>(hp.table)[c.first + t] = c.e[t];
 }
 
+// one thread per (chunk class, octave) tile prefix, one more for the band prefix
+static_assert(kNumTileH * kMaxOct + 1 <= 64, "k_finalize runs as one wave");
+
 __global__ void k_finalize(HdrPtrs hp, int n, DevParams p) {
   const ImgEntry* tab = hp.table;
   int* tp = hp.tile_prefix;

@@ -195,7 +195,7 @@ def test_tile_rows_do_not_change_results():
     imgs = [blobs(300 + k, h, w, 3 * DENSITY) for k, (h, w) in enumerate(sizes)]
     settings = dict(synth.BASE_SETTINGS, n_octaves=3, upsample=1)
     ref = None
-    for rows in (64, 128, 256, 512, 0):
+    for rows in (32, 64, 128, 256, 512, 0):
         say(f"tile_rows={rows}")
         ex = Extractor(dict(settings, tile_rows=rows))
         got = [digest(r[0], r[1]) + str(r[2:]) for r in extract_batch(ex, imgs)]
