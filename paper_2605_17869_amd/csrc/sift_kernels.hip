@@ -25,34 +25,44 @@ __global__ void k_setup(HdrPtrs hp, SetupChunk c) {
   if (t < c.count) const_cast<ImgEntry*>(hp.table)[c.first + t] = c.e[t];
 }
 
-// one thread per (chunk class, octave) tile prefix, one more for the band prefix
-static_assert(kNumTileH * kMaxOct + 1 <= 64, "k_finalize runs as one wave");
+// Prefix sums over the batch of the blur work items of every (chunk class,
+// octave) and of the detection bands, one wave, 64 images at a time: lane i
+// takes image i0 + i, each table is one wave scan, and lane t keeps the
+// running total of table t between chunks.
+static_assert(kNumTileH * kMaxOct + 1 <= 64, "one lane per table");
 
 __global__ void k_finalize(HdrPtrs hp, int n, DevParams p) {
   const ImgEntry* tab = hp.table;
-  int* tp = hp.tile_prefix;
-  int* bp = hp.band_prefix;
-  const int t = threadIdx.x;
-  if (t < kNumTileH * p.n_oct) {
-    // tile prefix for tile-height class t / n_oct, octave t % n_oct
-    const int cls = t / p.n_oct, k = t - cls * p.n_oct;
-    const int th = tile_h_of(cls);
-    int* out = tp + (cls * kMaxOct + k) * (n + 1);
-    int acc = 0;
-    out[0] = 0;
-    for (int i = 0; i < n; ++i) {
-      int hk, wk;
-      octave_dims(tab[i].h, tab[i].w, p.upsample, k, &hk, &wk);
-      acc += cdiv(wk, kTileW) * cdiv(hk, th);
-      out[i + 1] = acc;
-    }
-  } else if (t == kNumTileH * p.n_oct) {
-    const LayoutCfg lc = layout_cfg(p);
-    int acc = 0;
-    bp[0] = 0;
-    for (int i = 0; i < n; ++i) {
-      acc += region_tail(tab[i].h, tab[i].w, lc).total_bands;
-      bp[i + 1] = acc;
+  const LayoutCfg lc = layout_cfg(p);
+  const int lane = threadIdx.x;
+  const int ntile = kNumTileH * p.n_oct;   // tables 0 .. ntile - 1; the band table last
+  int run = 0;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const int i = i0 + lane;
+    const bool has = i < n;
+    const int h = has ? tab[i].h : 0, w = has ? tab[i].w : 0;
+    for (int t = 0; t <= ntile; ++t) {
+      int v = 0;
+      int* out;
+      if (t < ntile) {
+        // tile prefix for class t / n_oct, octave t % n_oct
+        const int cls = t / p.n_oct, k = t - cls * p.n_oct;
+        if (has) {
+          int hk, wk;
+          octave_dims(h, w, p.upsample, k, &hk, &wk);
+          v = cdiv(wk, kTileW) * cdiv(hk, tile_h_of(cls));
+        }
+        out = hp.tile_prefix + (cls * kMaxOct + k) * (n + 1);
+      } else {
+        if (has) v = region_tail(h, w, lc).total_bands;
+        out = hp.band_prefix;
+      }
+      const int incl = wave_incl_scan(v);
+      const int base = __shfl(run, t, 64);
+      if (i0 == 0 && lane == 0) out[0] = 0;
+      if (has) out[i + 1] = base + incl;
+      const int chunk = __shfl(incl, 63, 64);
+      if (lane == t) run += chunk;
     }
   }
 }
