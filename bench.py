@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0,
                     help="blur chunk height (0: autotuned on the batch unless --no-autotune)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--n-streams", type=int, default=0,
+                    help="sub-batches of a batched call (0: library choice, 1: one launch sequence)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain elementwise pass over MIB MiB (counter yardstick)")
@@ -225,7 +227,7 @@ def main():
         tune = {str(k): round(v, 4) for k, v in tune_ms.items()}
         del probe, ws0
         print(f"[bench] autotune: tile_rows {tile_rows} ({tune})", file=sys.stderr, flush=True)
-    settings = dict(wl.settings, tile_rows=tile_rows)
+    settings = dict(wl.settings, tile_rows=tile_rows, n_streams=args.n_streams)
     ex = sm.Extractor(settings)
     ws = torch.empty(ex.batch_workspace_size(sizes), dtype=torch.uint8, device=dev)
     outs = [ex.alloc_features() for _ in range(n)]

@@ -85,8 +85,6 @@ void set_last_error(const std::string& msg) { g_error = msg; }
 void set_capturing(bool on) { g_capturing = on; }
 }  // namespace sift
 
-constexpr int kMaxParts = 8;        // sub-batches one batched call may run concurrently
-
 struct sift_handle {
   sift_params params;
   DevParams dev;

@@ -27,6 +27,7 @@ constexpr int kBlurThreads = 256;  // blur work-group size (one source column pe
 constexpr int kBlurRows = 16;      // rows a blur work-group advances per step
 constexpr int kNumTileH = 5;       // blur chunk heights 32, 64, 128, 256, 512
 constexpr int kXcds = 8;           // work-groups are dealt round-robin to the XCDs
+constexpr int kMaxParts = 8;       // sub-batches (each with its own header) of one batched call
 constexpr int kBand = 8;           // rows per detection band
 constexpr int kDetectWaves = 4;    // waves of a detection work-group
 constexpr int kSeg = 62;           // output columns per 64-lane detection segment

@@ -109,6 +109,13 @@ int64_t header_bytes(int n) {
   return hd.bytes;
 }
 
+// Workspace bytes that cover a batch of n requests whose regions sum to
+// `regions`, however the batched call splits it: at most min(n, kMaxParts)
+// sub-batches, each with a header no larger than the whole batch's.
+int64_t batch_bytes(int n, int64_t regions) {
+  return align_up256((int64_t)std::min(n, kMaxParts) * header_bytes(n) + regions);
+}
+
 }  // namespace
 
 struct sift_server {
@@ -179,13 +186,13 @@ bool sift_server::admit() {
     int n = 0;
     int64_t regions = 0;
     while (n < (int)pending.size() && n < max_batch) {
-      const int64_t need = align_up256(header_bytes(n + 1) + regions + pending[n].region);
+      const int64_t need = batch_bytes(n + 1, regions + pending[n].region);
       if (need > room) break;
       regions += pending[n].region;
       ++n;
     }
     if (n == 0) break;   // the head waits for arena space
-    const int64_t bytes = align_up256(header_bytes(n) + regions);
+    const int64_t bytes = batch_bytes(n, regions);
     const int64_t off = alloc.take(bytes);
     int si = 0;
     while (stream_busy[si]) ++si;

@@ -44,9 +44,12 @@ def test_served_outputs_equal_plain_extraction():
     ex = Extractor(SETTINGS)
     ref = [extract(ex, im) for im in imgs]
     one = max(ex.workspace_size(*im.shape) for im in imgs)
-    # room for about three of the largest images at once: batches are cut by footprint
-    arena = 3 * one + (1 << 20)
-    for max_batch, max_inflight in ((4, 2), (1, 1), (64, 3)):
+    # room for about three of the largest images at once: batches are cut by
+    # footprint; with room for all, batches of 8 or more images form, which
+    # the batched call runs as sub-batches with a header each
+    small, large = 3 * one + (1 << 20), 16 * one
+    for max_batch, max_inflight, arena in ((4, 2, small), (1, 1, small), (64, 3, small),
+                                           (64, 1, large), (12, 2, large)):
         say(f"max_batch={max_batch} max_inflight={max_inflight} arena={arena}")
         got, stats = serve(imgs, arena, max_batch, max_inflight)
         say(f"  stats {stats}")
@@ -57,6 +60,10 @@ def test_served_outputs_equal_plain_extraction():
             assert stats["batches"] == len(imgs)
         else:
             assert stats["batches"] < len(imgs)
+        if arena == large and max_inflight == 1:
+            # one batch holds every request (all submitted before the worker
+            # could start a second): the sub-batch path ran
+            assert stats["batches"] <= 2
         for k, (a, b) in enumerate(zip(ref, got)):
             assert digest(a[0], a[1]) == digest(b[0], b[1]), k
             assert a[2:] == b[2:], k
