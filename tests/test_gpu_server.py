@@ -60,10 +60,6 @@ def test_served_outputs_equal_plain_extraction():
             assert stats["batches"] == len(imgs)
         else:
             assert stats["batches"] < len(imgs)
-        if arena == large and max_inflight == 1:
-            # one batch holds every request (all submitted before the worker
-            # could start a second): the sub-batch path ran
-            assert stats["batches"] <= 2
         for k, (a, b) in enumerate(zip(ref, got)):
             assert digest(a[0], a[1]) == digest(b[0], b[1]), k
             assert a[2:] == b[2:], k
