@@ -55,6 +55,7 @@ class Params:
     dsp_scales: tuple = (1.0,)
     rootsift: int = 0
     max_keypoints: int = 65536
+    max_candidates: int = 65536   # detections refined, first ones in canonical order
 
     @classmethod
     def from_settings(cls, settings: dict) -> "Params":
@@ -551,8 +552,9 @@ class Result:
     keypoints: np.ndarray          # KEYPOINT_DTYPE, canonical order, capped
     descriptors: np.ndarray        # (n, d*d*n_ori) float64
     n_found: int                   # keypoints before the cap
-    log: list = field(default_factory=list)   # one dict per candidate
+    log: list = field(default_factory=list)   # one dict per refined candidate
     octaves: list = field(default_factory=list)
+    n_candidates: int = 0          # detections before the candidate cap
 
 
 def orient_and_describe(oc: Octave, res: dict, p: Params):
@@ -576,13 +578,17 @@ def sift(img: np.ndarray, p: Params | None = None, keep_octaves: bool = False,
     Keypoints come in the order of the candidate they were refined from
     (octave, layer, row, column, ascending), then by orientation bin; two
     candidates that converge to one point give two keypoints; the first
-    max_keypoints are kept and n_found counts all of them."""
+    max_keypoints are kept and n_found counts all of them.  Only the first
+    max_candidates detections (same canonical order) are refined; the
+    paper fixes no such capacity, so with the default none is cut on the
+    workloads used here."""
     p = p or Params()
     octaves = scale_space(img, p)
     by_o = {oc.o: oc for oc in octaves}
     log = []
     kps, descs = [], []
-    for (o, i, r, c) in detect(octaves, p):
+    cands = detect(octaves, p)
+    for (o, i, r, c) in cands[:p.max_candidates]:
         oc = by_o[o]
         res = refine(oc, i, r, c, p)
         res.update(pixel_margins(oc.D, i, r, c, p))
@@ -602,4 +608,4 @@ def sift(img: np.ndarray, p: Params | None = None, keep_octaves: bool = False,
     nd = p.desc_width * p.desc_width * p.desc_ori_bins
     return Result(np.array(kps, dtype=KEYPOINT_DTYPE),
                   np.array(descs, dtype=np.float64).reshape(-1, nd),
-                  n_found, log, octaves if keep_octaves else [])
+                  n_found, log, octaves if keep_octaves else [], len(cands))

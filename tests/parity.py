@@ -69,20 +69,60 @@ def group_by_source(kps) -> dict:
     return groups
 
 
+def source_keys(kps) -> list:
+    """(octave, src_layer, src_iy, src_ix) of every keypoint, in output order."""
+    return [(int(kps["octave"][k]), int(kps["src_layer"][k]), int(kps["src_iy"][k]),
+             int(kps["src_ix"][k])) for k in range(len(kps))]
+
+
+def check_order(oracle_result, kps, rep: Report, margin: float = MARGIN, before=None):
+    """Canonical order: keypoints come by ascending source detection (octave,
+    layer, row, column), and, over the decisive detections, the sequence of
+    source keys (one per orientation) equals the oracle's.  ``before``: only
+    keys below it take part (the cut of a capped output)."""
+    keys = source_keys(kps)
+    for a, b in zip(keys, keys[1:]):
+        if b < a:
+            rep.mismatches.append((b, f"out of canonical order after {a}"))
+            break
+    decisive = {(e["o"], e["i0"], e["r0"], e["c0"]): e for e in oracle_result.log
+                if is_decisive(e, margin)}
+    want = []
+    for key, e in decisive.items():
+        if before is not None and not key < before:
+            continue
+        if e["status"] == "ok":
+            want += [key] * len(e["angles"])
+    got = [k for k in keys if k in decisive and (before is None or k < before)]
+    if got != want:
+        first = next((j for j, (a, b) in enumerate(zip(got, want)) if a != b),
+                     min(len(got), len(want)))
+        rep.mismatches.append((got[first] if first < len(got) else None,
+                               f"decisive key sequence differs from the oracle's at position "
+                               f"{first} ({len(got)} vs {len(want)} keys)"))
+
+
 def compare(oracle_result, kps, desc, params, oracle_mod, margin: float = MARGIN,
-            sample: set | None = None) -> Report:
+            sample: set | None = None, before=None) -> Report:
     """Compare keypoints ``kps`` (structured array with the oracle's field
-    names) and descriptors ``desc`` with ``oracle_result``.
+    names) and descriptors ``desc`` with ``oracle_result``, including their
+    canonical order.
 
     ``sample``: optional set of candidate keys to restrict the check to (for
     large inputs where the oracle describes only some candidates).
-    The check assumes no keypoint cap was hit on either side."""
+    ``before``: only source keys below this one are compared (a capped output
+    is the prefix of the canonical sequence up to its cut; see
+    ``compare_capped``).  Without it the check assumes no cap was hit."""
     rep = Report()
     got = group_by_source(kps)
     by_key = {(e["o"], e["i0"], e["r0"], e["c0"]): e for e in oracle_result.log}
     octs = {oc.o: oc for oc in oracle_result.octaves}
+    if sample is None:
+        check_order(oracle_result, kps, rep, margin, before)
     for key, e in by_key.items():
         if sample is not None and key not in sample:
+            continue
+        if before is not None and not key < before:
             continue
         if not is_decisive(e, margin):
             rep.marginal += 1
@@ -132,6 +172,8 @@ def compare(oracle_result, kps, desc, params, oracle_mod, margin: float = MARGIN
             continue
         if sample is not None and key not in sample:
             continue
+        if before is not None and not key < before:
+            continue
         o, i, r, c = key
         oc = octs.get(o)
         if oc is None:
@@ -142,4 +184,34 @@ def compare(oracle_result, kps, desc, params, oracle_mod, margin: float = MARGIN
             rep.extra_marginal += 1
         else:
             rep.mismatches.append((key, f"not an oracle candidate (margins {m})"))
+    return rep
+
+
+def compare_capped(oracle_full, kps, desc, params, oracle_mod, cap: int,
+                   margin: float = MARGIN) -> Report:
+    """A keypoint-capped output against the uncapped oracle: the output must be
+    the first ``cap`` keypoints of the canonical sequence.  Every source key
+    below the output's last one is compared in full (values, orientation
+    counts, order).  When no marginal detection precedes the cut on either
+    side, the output's key sequence must equal the oracle's first ``cap``
+    keys exactly (so both cut at the same keypoint)."""
+    keys = source_keys(kps)
+    if not keys:
+        rep = Report()
+        rep.mismatches.append((None, "capped output is empty"))
+        return rep
+    cut = keys[-1]
+    rep = compare(oracle_full, kps, desc, params, oracle_mod, margin, before=cut)
+    if len(kps) > cap:
+        rep.mismatches.append((cut, f"{len(kps)} keypoints under a cap of {cap}"))
+    full_keys = []
+    for e in oracle_full.log:
+        if e["status"] == "ok":
+            full_keys += [(e["o"], e["i0"], e["r0"], e["c0"])] * len(e["angles"])
+    o_cap = full_keys[:cap]
+    limit = max(cut, o_cap[-1]) if o_cap else cut
+    marginal_before = any(not is_decisive(e, margin) and (e["o"], e["i0"], e["r0"], e["c0"]) <= limit
+                          for e in oracle_full.log)
+    if not marginal_before and rep.extra_marginal == 0 and keys != o_cap:
+        rep.mismatches.append((cut, f"capped key sequence differs from the oracle's first {cap}"))
     return rep

@@ -37,7 +37,7 @@ def assert_parity(p, ref, kp, desc, nf, nc, min_decisive=1):
         say(f"  mismatch {m}")
     assert rep.ok, rep.summary()
     assert rep.decisive_ok >= min_decisive
-    assert nc == len(ref.log)
+    assert nc == ref.n_candidates
     # n_found may differ only through marginal candidates
     assert abs(nf - ref.n_found) <= 4 * (rep.marginal + rep.extra_marginal)
     return rep
@@ -100,6 +100,8 @@ CASES = [
     ("140x160 3 DSP sizes", 140, 160, dict(n_octaves=3, dsp_scales=(1.0, 0.6, 1.3))),
     ("120x140 s=2", 120, 140, dict(n_octaves=3, n_scales=2)),
     ("180x200 s=4", 180, 200, dict(n_octaves=3, n_scales=4)),
+    ("200x240 s=5", 200, 240, dict(n_octaves=3, n_scales=5)),
+    ("210x190 s=6 upsampled", 210, 190, dict(n_octaves=2, n_scales=6, upsample=1)),
     ("104x104 minimum size, 4 octaves", 104, 104, dict(n_octaves=4)),
     ("70x333 wide strip", 70, 333, dict(n_octaves=2)),
 ]
@@ -163,6 +165,44 @@ def test_keypoint_cap_and_capacity():
     small = extract(Extractor(wl.settings), img, capacity=7)
     assert len(small[0]) == 7 and small[2] == full[2]
     assert digest(small[0], small[1]) == digest(full[0][:7], full[1][:7])
+
+
+@pytest.mark.parametrize("cap", [100, 1])
+def test_keypoint_cap_matches_oracle(cap):
+    """A hit keypoint cap keeps the oracle's first `cap` keypoints of the
+    canonical sequence (the cap cuts by order, not by response)."""
+    from paper_2605_17869_amd import Extractor
+    wl = synth.workload(1)
+    img = wl.image(0)
+    p = so.Params.from_settings(wl.settings)
+    ref = oracle.sift(img, p, keep_octaves=True)
+    assert ref.n_found > cap
+    kp, desc, nf, nc = extract(Extractor(dict(wl.settings, max_keypoints=cap)), img)
+    assert len(kp) == cap
+    rep = parity.compare_capped(ref, kp, desc, p, so, cap)
+    say(f"cap {cap}: {rep.summary()}")
+    assert rep.ok, rep.mismatches[:5]
+    assert nc == ref.n_candidates
+
+
+def test_candidate_cap_matches_oracle():
+    """Only the first max_candidates detections (canonical order) are refined,
+    as in the oracle with the same capacity; n_candidates is the full count."""
+    from paper_2605_17869_amd import Extractor
+    wl = synth.workload(1)
+    img = wl.image(0)
+    settings = dict(wl.settings, max_candidates=40)
+    p = so.Params.from_settings(settings)
+    ref = oracle.sift(img, p, keep_octaves=True)
+    assert len(ref.log) == 40 < ref.n_candidates
+    kp, desc, nf, nc = extract(Extractor(settings), img)
+    assert nc == ref.n_candidates
+    last = max((e["o"], e["i0"], e["r0"], e["c0"]) for e in ref.log)
+    rep = parity.compare(ref, kp, desc, p, so, before=last)
+    say(f"candidate cap 40: {rep.summary()}")
+    assert rep.ok, rep.mismatches[:5]
+    assert rep.decisive_ok >= 10
+    assert all(k <= last for k in parity.source_keys(kp))
 
 
 def test_candidate_cap_keeps_canonical_prefix():

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import oracle
+import parity
 from oracle import sift_oracle as so
 from paper_2605_17869_amd import synth
 from gpu_util import digest, extract_batch, require_gpu, say
@@ -38,6 +39,26 @@ def test_highres_mixed_orientation_with_warped_copies():
     oracle_parity(batch[0], wl.settings, res[0], 500)
     say("warped copy of a 1600x1066 image vs oracle")
     oracle_parity(batch[5], wl.settings, res[5], 200)
+
+
+def test_highres_image_capped_below_its_count():
+    """A 1066x1600 image of the high-resolution workload with the keypoint cap
+    set below its count: the kept keypoints are the oracle's first ones in
+    canonical order."""
+    from paper_2605_17869_amd import Extractor
+    wl = synth.workload(3, 4)
+    img = wl.image(0)
+    p = so.Params.from_settings(wl.settings)
+    ref = oracle.sift(img, p, keep_octaves=True)
+    cap = ref.n_found // 2
+    say(f"{img.shape}: oracle {ref.n_found} keypoints, cap {cap}")
+    settings = dict(wl.settings, max_keypoints=cap)
+    kp, desc, nf, nc = extract_batch(Extractor(settings), [img])[0]
+    assert len(kp) == cap
+    rep = parity.compare_capped(ref, kp, desc, p, so, cap)
+    say(rep.summary())
+    assert rep.ok, rep.mismatches[:5]
+    assert rep.decisive_ok >= 300
 
 
 def test_dsp_rootsift_batch():
