@@ -57,7 +57,10 @@ typedef enum {
 /* Extraction settings.  sift_params_default() fills the values noted. */
 typedef struct {
   int32_t n_octaves;          /* 4: octaves 0..n_octaves-1 (plus -1 when upsample) */
-  int32_t n_scales;           /* 3: s, DoG layers searched per octave, 1..6 */
+  int32_t n_scales;           /* 3: s, DoG layers searched per octave, 1..6, provided
+                                 every incremental blur has radius ceil(4 sigma) <= 24
+                                 (with sigma0 1.6 that is s = 2..6; s = 1 would need 45
+                                 and gives SIFT_ERR_NOT_SUPPORTED) */
   int32_t upsample;           /* 0: 1 adds octave -1 from a 2x bilinear upsample */
   float sigma0;               /* 1.6: blur of level 0 of each octave, octave pixels */
   float sigma_in;             /* 0.5: blur assumed present in the input */
@@ -76,7 +79,12 @@ typedef struct {
   float desc_magnif;          /* 3.0: cell width / keypoint sigma */
   float desc_clamp;           /* 0.2: clamp after the first L2 normalisation */
   int32_t n_dsp;              /* 1: number of domain sizes pooled (1..SIFT_MAX_DSP) */
-  float dsp_scales[SIFT_MAX_DSP]; /* {1}: domain sizes relative to the keypoint scale */
+  float dsp_scales[SIFT_MAX_DSP]; /* {1}: domain sizes relative to the keypoint scale, in
+                                 (0, 64); the largest descriptor window that desc_magnif,
+                                 the largest size and the largest keypoint scale
+                                 (sigma0 * 2^((s + 1/2) / s)) can give must stay below
+                                 2048 samples a side, else SIFT_ERR_NOT_SUPPORTED (with
+                                 the defaults: sizes up to about 26) */
   int32_t rootsift;           /* 0: 1 applies L1 normalisation then sqrt */
   int32_t max_keypoints;      /* 65536: keypoints kept per image (canonical order) */
   int32_t max_candidates;     /* 65536: detections refined per image (canonical order) */
@@ -246,7 +254,10 @@ sift_status sift_autotune_batch(const sift_params* p, int32_t n, const float* co
  * the batch has at most max_batch images and its workspace fits in a free
  * arena range (admission by footprint), and launches it on one of
  * max_inflight streams of its own (default priority), so consecutive batches
- * overlap.  Each request's outputs are bit-identical to sift_extract on the
+ * overlap.  A batch is formed under the server's lock and its launch sequence
+ * enqueued with the lock released; every stream has its own handle, so the
+ * sub-batch streams of a large batch are never shared between batches in
+ * flight.  Each request's outputs are bit-identical to sift_extract on the
  * same image.
  *
  * sift_server_submit enqueues a request and returns at once with a ticket;
@@ -254,13 +265,19 @@ sift_status sift_autotune_batch(const sift_params* p, int32_t n, const float* co
  * until the ticket is done.  A request whose workspace alone exceeds the arena
  * gives SIFT_ERR_TOO_LARGE; size errors are reported as by sift_extract.
  * sift_server_poll reports whether a ticket is done and, once it is, its
- * latency (submit to observed completion, milliseconds) and forgets it;
- * sift_server_wait blocks until the ticket is done, then behaves as poll.
- * Unknown (or already reported) tickets give SIFT_ERR_INVALID_ARG.
- * sift_server_destroy finishes every pending and in-flight request, stops the
- * worker and releases the streams; the arena stays the caller's.  All server
- * calls are thread-safe.  max_batch 1 and max_inflight 1 serve requests one
- * at a time in arrival order (the plain per-image path).
+ * latency (from entry into sift_server_submit to observed completion,
+ * milliseconds) and forgets it; sift_server_wait blocks until the ticket is
+ * done, then behaves as poll.  Unknown (or already reported) tickets give
+ * SIFT_ERR_INVALID_ARG.  sift_server_destroy finishes every pending and
+ * in-flight request, stops the worker and releases the streams; the arena
+ * stays the caller's.  All server calls are thread-safe.  max_batch 1 and
+ * max_inflight 1 serve requests one at a time in arrival order (the plain
+ * per-image path).
+ *
+ * sift_server_batch_bytes (host arithmetic only) gives the arena bytes the
+ * server reserves for one batch of n images of the given sizes (host arrays):
+ * an arena of at least that many bytes can take them as one batch.  It is at
+ * least sift_batch_workspace_size for the same images, whatever n_streams.
  */
 typedef struct sift_server sift_server;
 
@@ -270,13 +287,26 @@ typedef struct {
   int64_t batches;        /* batches launched */
   int64_t peak_arena;     /* largest arena bytes in use at once */
   int64_t peak_inflight;  /* largest number of batches in flight at once */
+  int64_t largest_batch;  /* most images in one batch */
+  int64_t overlapped_batches;  /* batches launched while another was still in flight */
 } sift_server_stats;
+
+sift_status sift_server_batch_bytes(const sift_params* p, int32_t n, const int32_t* heights,
+                                    const int32_t* widths, size_t* bytes);
 
 sift_status sift_server_create(const sift_params* p, void* d_arena, size_t arena_bytes,
                                int32_t max_batch, int32_t max_inflight, sift_server** out);
 sift_status sift_server_submit(sift_server* s, const float* d_image, int32_t height,
                                int32_t width, int64_t pitch, const sift_output* out,
                                uint64_t* ticket);
+/* n requests at once (host arrays of n entries, as sift_extract_batch takes
+ * them): all are checked before any is queued (an error queues none), then
+ * they join the queue together, so a worker that is idle sees the whole group
+ * when it next forms a batch.  tickets[n] receives their tickets. */
+sift_status sift_server_submit_n(sift_server* s, int32_t n, const float* const* d_images,
+                                 const int32_t* heights, const int32_t* widths,
+                                 const int64_t* pitches, const sift_output* outs,
+                                 uint64_t* tickets);
 sift_status sift_server_poll(sift_server* s, uint64_t ticket, int32_t* done, double* latency_ms);
 sift_status sift_server_wait(sift_server* s, uint64_t ticket, double* latency_ms);
 sift_status sift_server_get_stats(sift_server* s, sift_server_stats* stats);

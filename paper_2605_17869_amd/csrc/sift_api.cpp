@@ -37,6 +37,7 @@ sift_status fail(sift_status st, const char* fmt, ...) {
 }
 
 constexpr int kMaxSide = 32768;    // per input dimension
+constexpr int kMaxWindowSide = 2047;   // orientation / descriptor window side, samples
 constexpr int kMaxBatch = 4096;
 
 // Chunk height class of a blur level: the tallest chunk, up to the caller's
@@ -134,6 +135,24 @@ sift_status validate_params(const sift_params& p) {
     return fail(SIFT_ERR_INVALID_ARG, "tile_rows must be 0, 32, 64, 128, 256 or 512");
   if (p.n_streams < 0 || p.n_streams > kMaxParts)
     return fail(SIFT_ERR_INVALID_ARG, "n_streams must be in 0..%d", kMaxParts);
+  // Window sizes.  A refined keypoint has layer + offset below s + 1/2, so
+  // its octave scale stays below sigma0 * 2^((s + 1/2) / s).  The descriptor
+  // scans a square of half-side ceil(2.5 * cell * (|cos| + |sin|)) + 1 for
+  // the largest domain size, the orientation histogram one of half-side
+  // floor(radius_factor * sigma_factor * sigma + 1/2); both sides are kept
+  // below 2048 samples (at most 4M samples per keypoint).
+  const double sig_max = p.sigma0 * std::pow(2.0, (p.n_scales + 0.5) / p.n_scales);
+  double dmax = 0.0;
+  for (int i = 0; i < p.n_dsp; ++i) dmax = std::max(dmax, (double)p.dsp_scales[i]);
+  const double rd = std::ceil(2.5 * std::sqrt(2.0) * p.desc_magnif * sig_max * dmax) + 1.0;
+  if (2.0 * rd + 1.0 > kMaxWindowSide)
+    return fail(SIFT_ERR_NOT_SUPPORTED,
+                "descriptor window side %.0f exceeds %d (desc_magnif * largest dsp_scale too large)",
+                2.0 * rd + 1.0, kMaxWindowSide);
+  const double ro = std::floor(p.ori_radius_factor * p.ori_sigma_factor * sig_max + 0.5);
+  if (2.0 * ro + 1.0 > kMaxWindowSide)
+    return fail(SIFT_ERR_NOT_SUPPORTED, "orientation window side %.0f exceeds %d",
+                2.0 * ro + 1.0, kMaxWindowSide);
   return SIFT_OK;
 }
 

@@ -760,10 +760,18 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int qq = q0 + 64 * u + lane;
-        // qq / side through fp32: exact for side < 2048 (the quotient is
-        // at least 0.5 / side away from an integer)
-        const int qy = (int)(((float)qq + 0.5f) * inv_side);
-        const int dy = qy - R, dx = qq - qy * side - R;
+        // qq / side: an fp32 estimate within one of the quotient, then one
+        // correction step on the remainder makes it exact
+        int qy = (int)(((float)qq + 0.5f) * inv_side);
+        int qx = qq - qy * side;
+        if (qx < 0) {
+          --qy;
+          qx += side;
+        } else if (qx >= side) {
+          ++qy;
+          qx -= side;
+        }
+        const int dy = qy - R, dx = qx - R;
         const int rr = kp.r + dy, cc = kp.c + dx;
         float xr0, yr0;
         rotate(dx, dy, xr0, yr0);

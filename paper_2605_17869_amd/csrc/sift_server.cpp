@@ -1,9 +1,12 @@
 // Continuous-batching server over sift_extract_batch: requests of any size
 // are admitted in arrival order into batches that fit a free range of a
 // caller-owned device arena, and launched on a few streams of the server's
-// own so consecutive batches overlap.  One host worker thread does the
-// admitting, launching and retiring; submit, poll and wait only touch the
-// shared queues under a mutex.
+// own so consecutive batches overlap.  One host worker thread admits,
+// launches and retires batches.  Batches are formed under the server mutex
+// but their launch sequences are enqueued outside it, so submit, poll and
+// wait never wait for a launch.  Each server stream has a handle of its own,
+// so the sub-batch streams a large batch forks onto are never shared by two
+// batches in flight.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,7 +14,6 @@
 #include <condition_variable>
 #include <cstdint>
 #include <deque>
-#include <map>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -20,6 +22,7 @@
 
 #include "../../include/sift.h"
 #include "sift_internal.h"
+#include "sift_sched.h"
 
 using namespace sift;
 
@@ -30,9 +33,6 @@ void set_last_error(const std::string& msg);
 namespace {
 
 using Clock = std::chrono::steady_clock;
-
-constexpr int64_t kAlign = 256;
-int64_t align_up256(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Request {
   uint64_t ticket;
@@ -55,71 +55,15 @@ struct Batch {
   std::vector<uint64_t> tickets;
 };
 
-// First-fit allocator over [0, size) in 256-byte units; free ranges coalesce.
-class Arena {
- public:
-  void reset(int64_t size) {
-    free_.clear();
-    if (size > 0) free_[0] = size;
-  }
-  int64_t largest() const {
-    int64_t m = 0;
-    for (const auto& f : free_) m = std::max(m, f.second);
-    return m;
-  }
-  int64_t take(int64_t bytes) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        const int64_t off = it->first, rest = it->second - bytes;
-        free_.erase(it);
-        if (rest > 0) free_[off + bytes] = rest;
-        return off;
-      }
-    }
-    return -1;
-  }
-  void give(int64_t off, int64_t bytes) {
-    auto it = free_.emplace(off, bytes).first;
-    auto next = std::next(it);
-    if (next != free_.end() && it->first + it->second == next->first) {
-      it->second += next->second;
-      free_.erase(next);
-    }
-    if (it != free_.begin()) {
-      auto prev = std::prev(it);
-      if (prev->first + prev->second == it->first) {
-        prev->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-
- private:
-  std::map<int64_t, int64_t> free_;
-};
-
 sift_status server_fail(sift_status st, const std::string& msg) {
   set_last_error(msg);
   return st;
 }
 
-int64_t header_bytes(int n) {
-  Header hd;
-  make_header(n, &hd);
-  return hd.bytes;
-}
-
-// Workspace bytes that cover a batch of n requests whose regions sum to
-// `regions`, however the batched call splits it: at most min(n, kMaxParts)
-// sub-batches, each with a header no larger than the whole batch's.
-int64_t batch_bytes(int n, int64_t regions) {
-  return align_up256((int64_t)std::min(n, kMaxParts) * header_bytes(n) + regions);
-}
-
 }  // namespace
 
 struct sift_server {
-  sift_handle* handle = nullptr;
+  std::vector<sift_handle*> handles;   // one per stream (each with its own sub-batch streams)
   char* arena = nullptr;
   int64_t arena_bytes = 0;
   int max_batch = 1, max_inflight = 1;
@@ -132,6 +76,7 @@ struct sift_server {
   std::condition_variable done_cv;  // waiters: a batch retired
   std::deque<Request> pending;
   std::vector<Batch> inflight;
+  int launching = 0;                // batches being enqueued outside the mutex
   std::unordered_map<uint64_t, Ticket> tickets;
   Arena alloc;
   int64_t arena_in_use = 0;
@@ -143,8 +88,25 @@ struct sift_server {
 
   void run();
   bool retire();
-  bool admit();
+  void launch_ready(std::unique_lock<std::mutex>& lk);
+  void end_batch(const Batch& b, Clock::time_point now);
 };
+
+// Marks a batch's tickets done and returns its arena range and stream.
+// Caller holds mu.
+void sift_server::end_batch(const Batch& b, Clock::time_point now) {
+  for (uint64_t t : b.tickets) {
+    auto it = tickets.find(t);
+    if (it != tickets.end()) {
+      it->second.done = true;
+      it->second.finished = now;
+    }
+  }
+  stats.completed += (int64_t)b.tickets.size();
+  alloc.give(b.offset, b.bytes);
+  arena_in_use -= b.bytes;
+  stream_busy[b.stream] = false;
+}
 
 // Retires finished batches; returns true if any retired.  Caller holds mu.
 bool sift_server::retire() {
@@ -157,42 +119,22 @@ bool sift_server::retire() {
     }
     if (q != hipSuccess && worker_error.empty())
       worker_error = std::string("batch completion: ") + hipGetErrorString(q);
-    const Clock::time_point now = Clock::now();
-    Batch& b = inflight[i];
-    for (uint64_t t : b.tickets) {
-      auto it = tickets.find(t);
-      if (it != tickets.end()) {
-        it->second.done = true;
-        it->second.finished = now;
-      }
-    }
-    stats.completed += (int64_t)b.tickets.size();
-    alloc.give(b.offset, b.bytes);
-    arena_in_use -= b.bytes;
-    stream_busy[b.stream] = false;
-    hipEventDestroy(b.event);
+    end_batch(inflight[i], Clock::now());
+    hipEventDestroy(inflight[i].event);
     inflight.erase(inflight.begin() + i);
     any = true;
   }
   return any;
 }
 
-// Forms and launches batches while a stream is free and the head request
-// fits; returns true if any launched.  Caller holds mu.
-bool sift_server::admit() {
-  bool any = false;
-  while (!pending.empty() && (int)inflight.size() < max_inflight) {
-    const int64_t room = alloc.largest();
-    int n = 0;
-    int64_t regions = 0;
-    while (n < (int)pending.size() && n < max_batch) {
-      const int64_t need = batch_bytes(n + 1, regions + pending[n].region);
-      if (need > room) break;
-      regions += pending[n].region;
-      ++n;
-    }
+// Forms batches while a stream is free and the head request fits, and
+// enqueues each one's launch sequence with mu released.  Called and returns
+// with mu held.
+void sift_server::launch_ready(std::unique_lock<std::mutex>& lk) {
+  while (!pending.empty() && (int)inflight.size() + launching < max_inflight) {
+    int64_t bytes = 0;
+    const int n = next_batch(pending, max_batch, alloc.largest(), &bytes);
     if (n == 0) break;   // the head waits for arena space
-    const int64_t bytes = batch_bytes(n, regions);
     const int64_t off = alloc.take(bytes);
     int si = 0;
     while (stream_busy[si]) ++si;
@@ -214,48 +156,50 @@ bool sift_server::admit() {
       b.tickets.push_back(r.ticket);
     }
     pending.erase(pending.begin(), pending.begin() + n);
-    const sift_status st = sift_extract_batch(handle, n, imgs.data(), hs.data(), ws.data(),
+    stream_busy[si] = true;
+    arena_in_use += bytes;
+    stats.batches += 1;
+    stats.largest_batch = std::max(stats.largest_batch, (int64_t)n);
+    if (!inflight.empty() || launching > 0) stats.overlapped_batches += 1;
+    stats.peak_arena = std::max(stats.peak_arena, arena_in_use);
+    ++launching;
+
+    lk.unlock();
+    const sift_status st = sift_extract_batch(handles[si], n, imgs.data(), hs.data(), ws.data(),
                                               ps.data(), arena + off, (size_t)bytes, outs.data(),
                                               streams[si]);
     hipError_t e = hipSuccess;
     if (st == SIFT_OK) e = hipEventCreateWithFlags(&b.event, hipEventDisableTiming);
     if (st == SIFT_OK && e == hipSuccess) e = hipEventRecord(b.event, streams[si]);
-    if (st != SIFT_OK || e != hipSuccess) {
-      if (worker_error.empty())
-        worker_error = st != SIFT_OK ? std::string("batch launch: ") + sift_last_error()
-                                     : std::string("batch event: ") + hipGetErrorString(e);
-      // nothing (more) was enqueued for this batch: the requests end here
-      const Clock::time_point now = Clock::now();
-      for (uint64_t t : b.tickets) {
-        tickets[t].done = true;
-        tickets[t].finished = now;
-      }
-      alloc.give(off, bytes);
-      if (st == SIFT_OK) {
-        hipStreamSynchronize(streams[si]);   // the batch's kernels did launch
-        if (e != hipSuccess && b.event) hipEventDestroy(b.event);
-      }
+    std::string err;
+    if (st != SIFT_OK) err = std::string("batch launch: ") + sift_last_error();
+    else if (e != hipSuccess) err = std::string("batch event: ") + hipGetErrorString(e);
+    if (!err.empty() && st == SIFT_OK) {
+      hipStreamSynchronize(streams[si]);   // the batch's kernels did launch
+      if (b.event) hipEventDestroy(b.event);
+      b.event = nullptr;
+    }
+    lk.lock();
+
+    --launching;
+    if (!err.empty()) {
+      // nothing (more) is in flight for this batch: its requests end here
+      if (worker_error.empty()) worker_error = err;
+      end_batch(b, Clock::now());
       done_cv.notify_all();
       continue;
     }
-    stream_busy[si] = true;
-    arena_in_use += bytes;
-    stats.batches += 1;
-    stats.peak_arena = std::max(stats.peak_arena, arena_in_use);
     inflight.push_back(std::move(b));
     stats.peak_inflight = std::max(stats.peak_inflight, (int64_t)inflight.size());
-    any = true;
   }
-  return any;
 }
 
 void sift_server::run() {
   hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    const bool retired = retire();
-    if (retired) done_cv.notify_all();
-    admit();
+    if (retire()) done_cv.notify_all();
+    launch_ready(lk);
     if (stop && pending.empty() && inflight.empty()) break;
     if (inflight.empty()) {
       // idle: sleep until a submit (or stop) arrives
@@ -270,23 +214,51 @@ void sift_server::run() {
 
 extern "C" {
 
+sift_status sift_server_batch_bytes(const sift_params* p, int32_t n, const int32_t* heights,
+                                    const int32_t* widths, size_t* bytes) {
+  if (!p || !heights || !widths || !bytes) return server_fail(SIFT_ERR_INVALID_ARG, "null argument");
+  if (n < 1) return server_fail(SIFT_ERR_INVALID_ARG, "batch size must be >= 1");
+  sift_handle* h = nullptr;
+  sift_status st = sift_create(p, &h);
+  if (st != SIFT_OK) return server_fail(st, sift_last_error());
+  const int64_t hdr1 = header_bytes(1);
+  int64_t regions = 0;
+  for (int i = 0; i < n && st == SIFT_OK; ++i) {
+    size_t one = 0;
+    st = sift_workspace_size(h, heights[i], widths[i], &one);
+    regions += (int64_t)one - hdr1;
+  }
+  sift_destroy(h);
+  if (st != SIFT_OK) return server_fail(st, sift_last_error());
+  *bytes = (size_t)batch_bytes(n, regions);
+  return SIFT_OK;
+}
+
 sift_status sift_server_create(const sift_params* p, void* d_arena, size_t arena_bytes,
                                int32_t max_batch, int32_t max_inflight, sift_server** out) {
   if (!p || !d_arena || !out) return server_fail(SIFT_ERR_INVALID_ARG, "null argument");
-  if (reinterpret_cast<uintptr_t>(d_arena) % kAlign != 0)
+  if (reinterpret_cast<uintptr_t>(d_arena) % kArenaAlign != 0)
     return server_fail(SIFT_ERR_INVALID_ARG, "arena must be 256-byte aligned");
   if (max_batch < 1 || max_batch > 4096)
     return server_fail(SIFT_ERR_INVALID_ARG, "max_batch must be in 1..4096");
   if (max_inflight < 1 || max_inflight > 8)
     return server_fail(SIFT_ERR_INVALID_ARG, "max_inflight must be in 1..8");
   *out = nullptr;
-  sift_handle* h = nullptr;
-  sift_status st = sift_create(p, &h);
-  if (st != SIFT_OK) return server_fail(st, sift_last_error());
   sift_server* s = new sift_server();
-  s->handle = h;
+  sift_status st = SIFT_OK;
+  for (int i = 0; i < max_inflight && st == SIFT_OK; ++i) {
+    sift_handle* h = nullptr;
+    st = sift_create(p, &h);
+    if (st == SIFT_OK) s->handles.push_back(h);
+  }
+  if (st != SIFT_OK) {
+    const std::string msg = sift_last_error();
+    for (sift_handle* h : s->handles) sift_destroy(h);
+    delete s;
+    return server_fail(st, msg);
+  }
   s->arena = static_cast<char*>(d_arena);
-  s->arena_bytes = (int64_t)arena_bytes / kAlign * kAlign;
+  s->arena_bytes = (int64_t)arena_bytes / kArenaAlign * kArenaAlign;
   s->max_batch = max_batch;
   s->max_inflight = max_inflight;
   s->alloc.reset(s->arena_bytes);
@@ -298,7 +270,7 @@ sift_status sift_server_create(const sift_params* p, void* d_arena, size_t arena
   }
   if (e != hipSuccess) {
     for (hipStream_t q : s->streams) hipStreamDestroy(q);
-    sift_destroy(h);
+    for (sift_handle* h : s->handles) sift_destroy(h);
     delete s;
     return server_fail(SIFT_ERR_HIP, std::string("server streams: ") + hipGetErrorString(e));
   }
@@ -308,37 +280,83 @@ sift_status sift_server_create(const sift_params* p, void* d_arena, size_t arena
   return SIFT_OK;
 }
 
-sift_status sift_server_submit(sift_server* s, const float* d_image, int32_t height, int32_t width,
-                               int64_t pitch, const sift_output* out, uint64_t* ticket) {
-  if (!s || !d_image || !out || !ticket) return server_fail(SIFT_ERR_INVALID_ARG, "null argument");
+}  // extern "C"
+
+namespace {
+
+// Checks one request and fills *r (all but its ticket).
+sift_status make_request(sift_server* s, const float* d_image, int32_t height, int32_t width,
+                         int64_t pitch, const sift_output* out, Request* r) {
+  if (!d_image || !out) return server_fail(SIFT_ERR_INVALID_ARG, "null argument");
   if (pitch < width) return server_fail(SIFT_ERR_INVALID_ARG, "pitch < width");
   if (!out->keypoints || !out->descriptors || !out->count || out->capacity < 0)
     return server_fail(SIFT_ERR_INVALID_ARG, "bad output buffers");
   size_t one = 0;
-  const sift_status st = sift_workspace_size(s->handle, height, width, &one);
+  const sift_status st = sift_workspace_size(s->handles[0], height, width, &one);
   if (st != SIFT_OK) return server_fail(st, sift_last_error());
   if ((int64_t)one > s->arena_bytes)
     return server_fail(SIFT_ERR_TOO_LARGE, "request workspace exceeds the arena");
-  Request r;
-  r.image = d_image;
-  r.h = height;
-  r.w = width;
-  r.pitch = pitch;
-  r.out = *out;
-  r.region = (int64_t)one - header_bytes(1);
+  r->image = d_image;
+  r->h = height;
+  r->w = width;
+  r->pitch = pitch;
+  r->out = *out;
+  r->region = (int64_t)one - header_bytes(1);
+  return SIFT_OK;
+}
+
+// Queues checked requests under one hold of the lock (the worker sees all of
+// them at once) and assigns their tickets.
+sift_status enqueue(sift_server* s, std::vector<Request>& reqs, Clock::time_point arrived,
+                    uint64_t* tickets) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return server_fail(SIFT_ERR_INVALID_ARG, "server is shutting down");
-    r.ticket = s->next_ticket++;
-    Ticket t;
-    t.submitted = Clock::now();
-    s->tickets.emplace(r.ticket, t);
-    s->pending.push_back(r);
-    s->stats.submitted += 1;
-    *ticket = r.ticket;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+      Request& r = reqs[i];
+      r.ticket = s->next_ticket++;
+      Ticket t;
+      t.submitted = arrived;
+      s->tickets.emplace(r.ticket, t);
+      s->pending.push_back(r);
+      s->stats.submitted += 1;
+      tickets[i] = r.ticket;
+    }
   }
   s->cv.notify_one();
   return SIFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sift_status sift_server_submit(sift_server* s, const float* d_image, int32_t height, int32_t width,
+                               int64_t pitch, const sift_output* out, uint64_t* ticket) {
+  // the request's latency counts from here, before any validation or lock
+  const Clock::time_point arrived = Clock::now();
+  if (!s || !ticket) return server_fail(SIFT_ERR_INVALID_ARG, "null argument");
+  std::vector<Request> reqs(1);
+  const sift_status st = make_request(s, d_image, height, width, pitch, out, &reqs[0]);
+  if (st != SIFT_OK) return st;
+  return enqueue(s, reqs, arrived, ticket);
+}
+
+sift_status sift_server_submit_n(sift_server* s, int32_t n, const float* const* d_images,
+                                 const int32_t* heights, const int32_t* widths,
+                                 const int64_t* pitches, const sift_output* outs,
+                                 uint64_t* tickets) {
+  const Clock::time_point arrived = Clock::now();
+  if (!s || !d_images || !heights || !widths || !pitches || !outs || !tickets)
+    return server_fail(SIFT_ERR_INVALID_ARG, "null argument");
+  if (n < 1) return server_fail(SIFT_ERR_INVALID_ARG, "n must be >= 1");
+  std::vector<Request> reqs(n);
+  for (int i = 0; i < n; ++i) {
+    const sift_status st = make_request(s, d_images[i], heights[i], widths[i], pitches[i],
+                                        &outs[i], &reqs[i]);
+    if (st != SIFT_OK) return st;
+  }
+  return enqueue(s, reqs, arrived, tickets);
 }
 
 namespace {
@@ -396,7 +414,7 @@ sift_status sift_server_destroy(sift_server* s) {
   if (s->worker.joinable()) s->worker.join();
   const std::string err = s->worker_error;
   for (hipStream_t q : s->streams) hipStreamDestroy(q);
-  sift_destroy(s->handle);
+  for (sift_handle* h : s->handles) sift_destroy(h);
   delete s;
   if (!err.empty()) return server_fail(SIFT_ERR_HIP, err);
   return SIFT_OK;

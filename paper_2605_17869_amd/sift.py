@@ -66,7 +66,8 @@ assert KEYPOINT_DTYPE.itemsize == 48
 class SiftServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("batches", ctypes.c_int64), ("peak_arena", ctypes.c_int64),
-                ("peak_inflight", ctypes.c_int64)]
+                ("peak_inflight", ctypes.c_int64), ("largest_batch", ctypes.c_int64),
+                ("overlapped_batches", ctypes.c_int64)]
 
 
 # name -> (restype, argtypes)
@@ -107,12 +108,23 @@ _SIGNATURES = {
                                           ctypes.c_int32, ctypes.c_int64,
                                           ctypes.POINTER(SiftOutput),
                                           ctypes.POINTER(ctypes.c_uint64)]),
+    "sift_server_submit_n": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_void_p),
+                                            ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.POINTER(SiftOutput),
+                                            ctypes.POINTER(ctypes.c_uint64)]),
     "sift_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
                                         ctypes.POINTER(ctypes.c_int32),
                                         ctypes.POINTER(ctypes.c_double)]),
     "sift_server_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64,
                                         ctypes.POINTER(ctypes.c_double)]),
     "sift_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SiftServerStats)]),
+    "sift_server_batch_bytes": (ctypes.c_int, [ctypes.POINTER(SiftParams), ctypes.c_int32,
+                                               ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.POINTER(ctypes.c_size_t)]),
     "sift_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sift_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_void_p),
@@ -396,6 +408,20 @@ class BatchGraph:
             pass
 
 
+def server_batch_bytes(settings: dict | None, sizes) -> int:
+    """Arena bytes a server reserves for one batch of images of ``sizes``
+    ((height, width) pairs): ``sift_server_batch_bytes``."""
+    lib = load_library()
+    p = make_params(settings)
+    n = len(sizes)
+    hs = (ctypes.c_int32 * n)(*[int(h) for h, _ in sizes])
+    ws = (ctypes.c_int32 * n)(*[int(w) for _, w in sizes])
+    out = ctypes.c_size_t()
+    _check(lib.sift_server_batch_bytes(ctypes.byref(p), n, hs, ws, ctypes.byref(out)),
+           "sift_server_batch_bytes")
+    return out.value
+
+
 class Server:
     """Continuous-batching server (``sift_server_*``) over a torch-allocated
     device arena.  ``submit`` returns a ticket at once; ``wait`` / ``poll``
@@ -439,6 +465,27 @@ class Server:
                "sift_server_submit")
         self._held[t.value] = (image, f)
         return t.value
+
+    def submit_many(self, images, outs=None) -> list:
+        """Enqueue several 2-D float32 CUDA tensors as one group (they join
+        the queue together); returns their tickets."""
+        import torch
+        n = len(images)
+        for im in images:
+            if im.dim() != 2 or im.dtype != torch.float32 or not im.is_cuda or im.stride(1) != 1:
+                raise ValueError("images must be 2-D float32 CUDA tensors with contiguous rows")
+        feats = list(outs) if outs is not None else [self.alloc_features() for _ in range(n)]
+        ptrs = (ctypes.c_void_p * n)(*[im.data_ptr() for im in images])
+        hs = (ctypes.c_int32 * n)(*[im.shape[0] for im in images])
+        ws = (ctypes.c_int32 * n)(*[im.shape[1] for im in images])
+        ps = (ctypes.c_int64 * n)(*[im.stride(0) for im in images])
+        os_ = (SiftOutput * n)(*[Extractor._output(f, f.keypoints.shape[0]) for f in feats])
+        ts = (ctypes.c_uint64 * n)()
+        _check(self.lib.sift_server_submit_n(self.handle, n, ptrs, hs, ws, ps, os_, ts),
+               "sift_server_submit_n")
+        for k in range(n):
+            self._held[ts[k]] = (images[k], feats[k])
+        return list(ts)
 
     def poll(self, ticket: int):
         """(done, latency_ms, features) -- latency and features once done."""

@@ -40,6 +40,8 @@ PROBE = r"""
 int main(void) {
   printf("sift_params %zu\nsift_keypoint %zu\nsift_output %zu\nsift_stage_stat %zu\n",
          sizeof(sift_params), sizeof(sift_keypoint), sizeof(sift_output), sizeof(sift_stage_stat));
+  printf("sift_server_stats %zu\n", sizeof(sift_server_stats));
+  F(sift_server_stats, largest_batch); F(sift_server_stats, overlapped_batches);
   F(sift_params, dsp_scales); F(sift_params, rootsift); F(sift_params, max_candidates);
   F(sift_keypoint, octave); F(sift_keypoint, src_ix);
   F(sift_output, n_candidates); F(sift_output, capacity);
@@ -61,12 +63,13 @@ def test_struct_layouts_match_the_binding(tmp_path):
     assert int(out["sift_keypoint"]) == S.KEYPOINT_DTYPE.itemsize == 48
     assert int(out["sift_output"]) == ctypes.sizeof(S.SiftOutput)
     assert int(out["sift_stage_stat"]) == ctypes.sizeof(S.SiftStageStat)
+    assert int(out["sift_server_stats"]) == ctypes.sizeof(S.SiftServerStats)
     for key, val in out.items():
         if "." not in key:
             continue
         t, m = key.split(".")
         cls = {"sift_params": S.SiftParams, "sift_output": S.SiftOutput,
-               "sift_stage_stat": S.SiftStageStat}.get(t)
+               "sift_stage_stat": S.SiftStageStat, "sift_server_stats": S.SiftServerStats}.get(t)
         if cls is not None:
             assert getattr(cls, m).offset == int(val), key
         else:
@@ -189,7 +192,7 @@ def test_server_argument_errors_return_before_any_device_call():
     st = S.SiftServerStats()
     assert lib.sift_server_get_stats(None, ctypes.byref(st)) == 1
     assert lib.sift_server_destroy(None) == 0
-    assert ctypes.sizeof(S.SiftServerStats) == 40
+    assert ctypes.sizeof(S.SiftServerStats) == 56
 
 
 def test_graph_and_autotune_argument_errors():
@@ -204,3 +207,24 @@ def test_graph_and_autotune_argument_errors():
                                    ctypes.byref(best), None) == 1
     assert lib.sift_autotune_batch(ctypes.byref(p), 1, None, None, None, None, None, 0, None,
                                    None, 1, 0, ctypes.byref(best), None) == 1
+
+
+def test_window_and_scale_limits():
+    """Settings whose windows or blur radii the kernels cannot cover are
+    refused at create time: s = 1 (an incremental blur of radius 45), a
+    descriptor window of 2048 samples or more a side (desc_magnif x largest
+    domain size x largest keypoint scale), an orientation window as large."""
+    lib = S.load_library()
+    h = ctypes.c_void_p()
+    for bad in (dict(n_scales=1), dict(dsp_scales=[1.0, 30.0]), dict(desc_magnif=90.0),
+                dict(ori_radius_factor=200.0)):
+        pp = S.make_params(**bad)
+        assert lib.sift_create(ctypes.byref(pp), ctypes.byref(h)) == 6, bad
+        assert b"exceeds" in lib.sift_last_error(), bad
+    # the largest keypoint scale at s = 3 is 1.6 * 2^(3.5/3) = 3.59 px: a
+    # domain size of 26 gives a descriptor half-side ceil(2.5 sqrt 2 * 3 *
+    # 3.59 * 26) + 1 = 992, inside the limit; 27 gives 1030, outside
+    for ok in (dict(n_scales=2), dict(n_scales=5), dict(n_scales=6), dict(dsp_scales=[26.0])):
+        S.Extractor(**ok)
+    pp = S.make_params(dsp_scales=[27.5])
+    assert lib.sift_create(ctypes.byref(pp), ctypes.byref(h)) == 6

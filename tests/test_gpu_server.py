@@ -20,14 +20,14 @@ def requests(seed, n):
             for k, (h, w) in enumerate(sizes)]
 
 
-def serve(imgs, arena_bytes, max_batch, max_inflight):
+def serve(imgs, arena_bytes, max_batch, max_inflight, group=False):
     torch = require_gpu()
     from paper_2605_17869_amd import Server
     srv = Server(SETTINGS, arena_bytes=arena_bytes, max_batch=max_batch,
                  max_inflight=max_inflight)
     d = [torch.from_numpy(im).cuda() for im in imgs]
     torch.cuda.synchronize()
-    tickets = [srv.submit(t) for t in d]
+    tickets = srv.submit_many(d) if group else [srv.submit(t) for t in d]
     results = []
     for t in tickets:
         lat, f = srv.wait(t)
@@ -48,18 +48,23 @@ def test_served_outputs_equal_plain_extraction():
     # footprint; with room for all, batches of 8 or more images form, which
     # the batched call runs as sub-batches with a header each
     small, large = 3 * one + (1 << 20), 16 * one
-    for max_batch, max_inflight, arena in ((4, 2, small), (1, 1, small), (64, 3, small),
-                                           (64, 1, large), (12, 2, large)):
-        say(f"max_batch={max_batch} max_inflight={max_inflight} arena={arena}")
-        got, stats = serve(imgs, arena, max_batch, max_inflight)
+    for max_batch, max_inflight, arena, group in ((4, 2, small, False), (1, 1, small, False),
+                                                  (64, 3, small, False), (64, 1, large, True),
+                                                  (12, 2, large, True), (64, 2, large, False)):
+        say(f"max_batch={max_batch} max_inflight={max_inflight} arena={arena} group={group}")
+        got, stats = serve(imgs, arena, max_batch, max_inflight, group)
         say(f"  stats {stats}")
         assert stats["submitted"] == stats["completed"] == len(imgs)
         assert stats["peak_arena"] <= arena
         assert stats["peak_inflight"] <= max_inflight
+        assert stats["largest_batch"] <= max_batch
         if max_batch == 1:
             assert stats["batches"] == len(imgs)
-        else:
-            assert stats["batches"] < len(imgs)
+        if group:
+            # the whole group reaches an idle worker at once: with room for
+            # all, the first batch takes min(max_batch, 14) requests, a batch
+            # of 8 or more that the batched call splits into sub-batches
+            assert stats["largest_batch"] == min(max_batch, len(imgs)) >= 8
         for k, (a, b) in enumerate(zip(ref, got)):
             assert digest(a[0], a[1]) == digest(b[0], b[1]), k
             assert a[2:] == b[2:], k
