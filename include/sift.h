@@ -96,6 +96,12 @@ typedef struct {
                                  sub-batches on the handle's own streams, concurrently);
                                  1..8: that many sub-batches.  Any value gives bit-identical
                                  results (tuning only) */
+  int32_t upsample_max_pixels; /* 0: no limit.  With upsample = 1, an image of more than
+                                 this many pixels (height * width) is extracted without the
+                                 upsampled octave -1, exactly as with upsample = 0: the
+                                 paper's VRAM-adaptive suppression of the 2x base, which it
+                                 applies above 4 MP (4000000) on a 4 GB GPU.  A batch may
+                                 mix both kinds of image */
 } sift_params;
 
 /* One keypoint, 48 bytes.  Keypoints of an image come in canonical order:

@@ -18,7 +18,7 @@ checker can tell a decisive outcome from one that a rounding change could flip.
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field, fields
+from dataclasses import dataclass, field, fields, replace
 
 import numpy as np
 
@@ -56,6 +56,7 @@ class Params:
     rootsift: int = 0
     max_keypoints: int = 65536
     max_candidates: int = 65536   # detections refined, first ones in canonical order
+    upsample_max_pixels: int = 0  # > 0: no octave -1 for images of more pixels than this
 
     @classmethod
     def from_settings(cls, settings: dict) -> "Params":
@@ -184,6 +185,16 @@ def octave_shapes(height: int, width: int, p: Params):
     return shapes
 
 
+def effective_params(height: int, width: int, p: Params) -> Params:
+    """The settings an image is extracted with.  The paper's VRAM-adaptive
+    execution drops the 2x upsampled base for inputs above a size (4 MP on
+    its 4 GB GPU): with upsample_max_pixels > 0, an image of more pixels than
+    that is processed exactly as with upsample = 0."""
+    if p.upsample and p.upsample_max_pixels > 0 and height * width > p.upsample_max_pixels:
+        return replace(p, upsample=0)
+    return p
+
+
 def check_size(height: int, width: int, p: Params):
     last = octave_shapes(height, width, p)[-1]
     if min(last) < 2 * p.border + 3:
@@ -194,6 +205,7 @@ def scale_space(img: np.ndarray, p: Params) -> list:
     """Gaussian and DoG pyramid.  The next octave's level 0 is level s of the
     current octave taken at every second pixel, with no further blur."""
     img = np.asarray(img, dtype=np.float32).astype(np.float64)
+    p = effective_params(img.shape[0], img.shape[1], p)
     check_size(img.shape[0], img.shape[1], p)
     sigma_init, incs = level_sigmas(p)
     base = upsample2x(img) if p.upsample else img
@@ -583,6 +595,7 @@ def sift(img: np.ndarray, p: Params | None = None, keep_octaves: bool = False,
     paper fixes no such capacity, so with the default none is cut on the
     workloads used here."""
     p = p or Params()
+    p = effective_params(np.shape(img)[0], np.shape(img)[1], p)
     octaves = scale_space(img, p)
     by_o = {oc.o: oc for oc in octaves}
     log = []

@@ -86,14 +86,21 @@ void set_last_error(const std::string& msg) { g_error = msg; }
 void set_capturing(bool on) { g_capturing = on; }
 }  // namespace sift
 
+// Device settings and Gaussian taps of one octave structure.
+struct Config {
+  DevParams dev;
+  Taps init;                       // first level of the first octave
+  Taps inc[kMaxScales + 2];        // level i from level i-1, i = 1..s+2
+};
+
 struct sift_handle {
   sift_params params;
-  DevParams dev;
+  // cfg[0]: the settings as given; cfg[1]: the same without the upsampled
+  // octave, for images above upsample_max_pixels (the VRAM-adaptive policy)
+  Config cfg[2];
   hipStream_t part_stream[kMaxParts] = {};   // created by the first split batch
   std::once_flag streams_once;
   hipError_t streams_status = hipSuccess;
-  Taps init;                       // first level of the first octave
-  Taps inc[kMaxScales + 2];        // level i from level i-1, i = 1..s+2
 };
 
 namespace {
@@ -135,6 +142,8 @@ sift_status validate_params(const sift_params& p) {
     return fail(SIFT_ERR_INVALID_ARG, "tile_rows must be 0, 32, 64, 128, 256 or 512");
   if (p.n_streams < 0 || p.n_streams > kMaxParts)
     return fail(SIFT_ERR_INVALID_ARG, "n_streams must be in 0..%d", kMaxParts);
+  if (p.upsample_max_pixels < 0)
+    return fail(SIFT_ERR_INVALID_ARG, "upsample_max_pixels must be >= 0");
   // Window sizes.  A refined keypoint has layer + offset below s + 1/2, so
   // its octave scale stays below sigma0 * 2^((s + 1/2) / s).  The descriptor
   // scans a square of half-side ceil(2.5 * cell * (|cos| + |sin|)) + 1 for
@@ -156,26 +165,40 @@ sift_status validate_params(const sift_params& p) {
   return SIFT_OK;
 }
 
+// Which octave structure an image gets: without the upsampled octave when
+// the handle upsamples but the image has more than upsample_max_pixels pixels
+// (the paper's VRAM-adaptive suppression of the 2x base above a size).
+int cfg_index(const sift_handle* h, int height, int width) {
+  const sift_params& p = h->params;
+  return (p.upsample && p.upsample_max_pixels > 0 &&
+          (int64_t)height * width > (int64_t)p.upsample_max_pixels) ? 1 : 0;
+}
+
+const Config& cfg_for(const sift_handle* h, int height, int width) {
+  return h->cfg[cfg_index(h, height, width)];
+}
+
 // Octave count, size limits and the last-octave minimum.
 sift_status validate_size(const sift_handle* h, int height, int width) {
   if (height < 1 || width < 1) return fail(SIFT_ERR_INVALID_ARG, "image size must be positive");
   if (height > kMaxSide || width > kMaxSide)
     return fail(SIFT_ERR_TOO_LARGE, "image side above %d", kMaxSide);
+  const DevParams& d = cfg_for(h, height, width).dev;
   int hk, wk;
   // kernels address a level with 32-bit byte offsets: the first (largest)
   // level plane must stay below 2 GiB
-  octave_dims(height, width, h->dev.upsample, 0, &hk, &wk);
+  octave_dims(height, width, d.upsample, 0, &hk, &wk);
   if ((int64_t)hk * level_pitch(wk) * 4 >= (int64_t(1) << 31))
     return fail(SIFT_ERR_TOO_LARGE, "a %dx%d level exceeds 2 GiB", hk, wk);
-  octave_dims(height, width, h->dev.upsample, h->dev.n_oct - 1, &hk, &wk);
-  const int need = 2 * h->dev.border + 3;
+  octave_dims(height, width, d.upsample, d.n_oct - 1, &hk, &wk);
+  const int need = 2 * d.border + 3;
   if (hk < need || wk < need)
     return fail(SIFT_ERR_IMAGE_TOO_SMALL, "last octave %dx%d below %dx%d", hk, wk, need, need);
   return SIFT_OK;
 }
 
 int64_t region_bytes(const sift_handle* h, int height, int width) {
-  return region_tail(height, width, layout_cfg(h->dev)).bytes;
+  return region_tail(height, width, layout_cfg(cfg_for(h, height, width).dev)).bytes;
 }
 
 sift_status check_hip(hipError_t e, const char* what) {
@@ -237,24 +260,30 @@ void prof_end(int rec, hipStream_t stream) {
 }
 
 
-// Sub-batches of one batched call: contiguous index ranges of about equal
-// workspace footprint.  With several, they run on the handle's streams
-// concurrently (one image's arithmetic never depends on the others).
-int batch_parts(int32_t n, int parts_wanted, int* first) {
-  int parts = parts_wanted;
+// Sub-batches of one batched call.  An image's arithmetic never depends on
+// the others, so any partition gives the same bits; each part runs as one
+// launch sequence (several run concurrently on the handle's streams).
+struct Part {
+  int cfg;                  // octave structure of every image of the part
+  std::vector<int> idx;     // image indices, ascending
+};
+
+// Number of parts a batch of n images of one octave structure is cut into.
+int parts_wanted(int32_t n, int n_streams) {
+  int parts = n_streams;
   if (parts < 1) parts = n >= 8 ? 4 : 1;
-  parts = std::min(std::min(parts, kMaxParts), (int)n);
-  first[0] = 0;
-  first[parts] = n;
-  if (parts == 1) return 1;
-  return parts;
+  return std::min(std::min(parts, kMaxParts), (int)n);
 }
 
-void split_parts(const sift_handle* h, int32_t n, const int32_t* heights, const int32_t* widths,
-                 int parts, int* first) {
+// Contiguous ranges of `ids` of about equal workspace footprint.
+void split_even(const sift_handle* h, int cfg, const std::vector<int>& ids, int parts,
+                const int32_t* heights, const int32_t* widths, std::vector<Part>* out) {
+  const int n = (int)ids.size();
   int64_t total = 0;
   std::vector<int64_t> rb(n);
-  for (int i = 0; i < n; ++i) total += (rb[i] = region_bytes(h, heights[i], widths[i]));
+  for (int i = 0; i < n; ++i) total += (rb[i] = region_bytes(h, heights[ids[i]], widths[ids[i]]));
+  std::vector<int> first(parts + 1, n);
+  first[0] = 0;
   int64_t acc = 0;
   int p = 1;
   for (int i = 0; i < n && p < parts; ++i) {
@@ -264,15 +293,38 @@ void split_parts(const sift_handle* h, int32_t n, const int32_t* heights, const 
     if (acc * parts >= total * p && n - (i + 1) >= parts - p) first[p++] = i + 1;
   }
   while (p < parts) { first[p] = first[p - 1] + 1; ++p; }   // degenerate footprints
-  first[parts] = n;
+  for (int q = 0; q < parts; ++q) {
+    Part pt;
+    pt.cfg = cfg;
+    pt.idx.assign(ids.begin() + first[q], ids.begin() + first[q + 1]);
+    out->push_back(std::move(pt));
+  }
 }
 
-int64_t part_bytes(const sift_handle* h, int lo, int hi, const int32_t* heights,
+// The parts of a batch: images of one octave structure are split into
+// parts_wanted() ranges (one range when `one_sequence`); a batch that mixes
+// both structures runs one part per structure.
+std::vector<Part> plan_parts(const sift_handle* h, int32_t n, const int32_t* heights,
+                             const int32_t* widths, bool one_sequence) {
+  std::vector<int> ids[2];
+  for (int i = 0; i < n; ++i) ids[cfg_index(h, heights[i], widths[i])].push_back(i);
+  std::vector<Part> parts;
+  if (!ids[0].empty() && !ids[1].empty()) {
+    for (int c = 0; c < 2; ++c) split_even(h, c, ids[c], 1, heights, widths, &parts);
+    return parts;
+  }
+  const int c = ids[0].empty() ? 1 : 0;
+  const int np = one_sequence ? 1 : parts_wanted(n, h->params.n_streams);
+  split_even(h, c, ids[c], np, heights, widths, &parts);
+  return parts;
+}
+
+int64_t part_bytes(const sift_handle* h, const Part& pt, const int32_t* heights,
                    const int32_t* widths) {
   Header hd;
-  make_header(hi - lo, &hd);
+  make_header((int)pt.idx.size(), &hd);
   int64_t b = hd.bytes;
-  for (int i = lo; i < hi; ++i) b += region_bytes(h, heights[i], widths[i]);
+  for (int i : pt.idx) b += region_bytes(h, heights[i], widths[i]);
   return b;
 }
 
@@ -317,40 +369,45 @@ sift_status sift_create(const sift_params* p, sift_handle** out) {
   if (st != SIFT_OK) return st;
   sift_handle* h = new sift_handle();
   h->params = *p;
-  DevParams& d = h->dev;
-  std::memset(&d, 0, sizeof d);
-  d.n_oct = p->n_octaves + p->upsample;
-  d.o0 = p->upsample ? -1 : 0;
-  d.s = p->n_scales;
-  d.upsample = p->upsample;
-  d.border = p->border;
-  d.refine_iters = p->refine_iters;
-  d.upright = p->upright;
-  d.rootsift = p->rootsift;
-  d.max_kp = p->max_keypoints;
-  d.max_cand = p->max_candidates;
-  d.n_dsp = p->n_dsp;
-  d.sigma0 = p->sigma0;
-  d.contrast_thr = p->contrast_threshold;
-  d.pre_thr = p->prefilter_ratio * p->contrast_threshold;
-  d.edge_ratio = p->edge_ratio;
-  d.ori_sigma_factor = p->ori_sigma_factor;
-  d.ori_radius_factor = p->ori_radius_factor;
-  d.ori_peak_ratio = p->ori_peak_ratio;
-  d.desc_magnif = p->desc_magnif;
-  d.desc_clamp = p->desc_clamp;
-  // largest domain size first: the descriptor kernel stops its size loop at
-  // the first size whose window holds none of a batch's pixels
-  for (int i = 0; i < p->n_dsp; ++i) d.dsp[i] = p->dsp_scales[i];
-  std::sort(d.dsp, d.dsp + p->n_dsp, [](float a, float b) { return a > b; });
-  // level sigmas: level i of an octave carries sigma0 * k^i, k = 2^(1/s)
-  const double s0 = p->sigma0;
-  const double assumed = (double)p->sigma_in * (p->upsample ? 2.0 : 1.0);
-  const double sig_init = std::sqrt(std::fmax(s0 * s0 - assumed * assumed, 0.01));
-  const double k2 = std::pow(2.0, 2.0 / p->n_scales);
-  bool ok = make_taps(sig_init, &h->init);
-  for (int i = 1; i <= p->n_scales + 2; ++i)
-    ok = ok && make_taps(s0 * std::sqrt(std::pow(k2, i) - std::pow(k2, i - 1)), &h->inc[i - 1]);
+  bool ok = true;
+  for (int c = 0; c < 2; ++c) {
+    const int up = c == 0 ? p->upsample : 0;
+    DevParams& d = h->cfg[c].dev;
+    std::memset(&d, 0, sizeof d);
+    d.n_oct = p->n_octaves + up;
+    d.o0 = up ? -1 : 0;
+    d.s = p->n_scales;
+    d.upsample = up;
+    d.border = p->border;
+    d.refine_iters = p->refine_iters;
+    d.upright = p->upright;
+    d.rootsift = p->rootsift;
+    d.max_kp = p->max_keypoints;
+    d.max_cand = p->max_candidates;
+    d.n_dsp = p->n_dsp;
+    d.sigma0 = p->sigma0;
+    d.contrast_thr = p->contrast_threshold;
+    d.pre_thr = p->prefilter_ratio * p->contrast_threshold;
+    d.edge_ratio = p->edge_ratio;
+    d.ori_sigma_factor = p->ori_sigma_factor;
+    d.ori_radius_factor = p->ori_radius_factor;
+    d.ori_peak_ratio = p->ori_peak_ratio;
+    d.desc_magnif = p->desc_magnif;
+    d.desc_clamp = p->desc_clamp;
+    // largest domain size first: the descriptor kernel stops its size loop at
+    // the first size whose window holds none of a batch's pixels
+    for (int i = 0; i < p->n_dsp; ++i) d.dsp[i] = p->dsp_scales[i];
+    std::sort(d.dsp, d.dsp + p->n_dsp, [](float a, float b) { return a > b; });
+    // level sigmas: level i of an octave carries sigma0 * k^i, k = 2^(1/s)
+    const double s0 = p->sigma0;
+    const double assumed = (double)p->sigma_in * (up ? 2.0 : 1.0);
+    const double sig_init = std::sqrt(std::fmax(s0 * s0 - assumed * assumed, 0.01));
+    const double k2 = std::pow(2.0, 2.0 / p->n_scales);
+    ok = ok && make_taps(sig_init, &h->cfg[c].init);
+    for (int i = 1; i <= p->n_scales + 2; ++i)
+      ok = ok && make_taps(s0 * std::sqrt(std::pow(k2, i) - std::pow(k2, i - 1)),
+                           &h->cfg[c].inc[i - 1]);
+  }
   if (!ok) {
     delete h;
     return fail(SIFT_ERR_NOT_SUPPORTED, "a Gaussian radius ceil(4 sigma) exceeds %d", kMaxRadius);
@@ -381,17 +438,16 @@ sift_status sift_batch_workspace_size(const sift_handle* h, int32_t n, const int
     sift_status st = validate_size(h, heights[i], widths[i]);
     if (st != SIFT_OK) return st;
   }
-  // the sub-batches' layouts one after another (covers the one-part layout)
-  int first[kMaxParts + 1];
-  const int parts = batch_parts(n, h->params.n_streams, first);
-  if (parts > 1) split_parts(h, n, heights, widths, parts, first);
-  int64_t total = 0;
-  for (int q = 0; q < parts; ++q) total += part_bytes(h, first[q], first[q + 1], heights, widths);
-  Header hd;
-  make_header(n, &hd);
-  int64_t one = hd.bytes;
-  for (int i = 0; i < n; ++i) one += region_bytes(h, heights[i], widths[i]);
-  *bytes = (size_t)std::max(total, one);
+  // the parts' layouts one after another, for the split and for the
+  // one-sequence plan (stage profiling runs a batch as one sequence)
+  int64_t most = 0;
+  for (bool one : {false, true}) {
+    int64_t total = 0;
+    for (const Part& pt : plan_parts(h, n, heights, widths, one))
+      total += part_bytes(h, pt, heights, widths);
+    most = std::max(most, total);
+  }
+  *bytes = (size_t)most;
   return SIFT_OK;
 }
 
@@ -404,13 +460,13 @@ sift_status sift_workspace_size(const sift_handle* h, int32_t height, int32_t wi
 namespace {
 
 // The launch sequence of one (sub-)batch on `stream`; arguments already checked.
-sift_status launch_batch(sift_handle* h, int32_t n, const float* const* d_images,
-                         const int32_t* heights, const int32_t* widths, const int64_t* pitches,
-                         void* d_workspace, const sift_output* outs, void* stream_v) {
+sift_status launch_batch(const sift_handle* h, const Config& cfg, int32_t n,
+                         const float* const* d_images, const int32_t* heights,
+                         const int32_t* widths, const int64_t* pitches, void* d_workspace,
+                         const sift_output* outs, hipStream_t stream) {
   sift_status st = SIFT_OK;
-  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
   char* ws = static_cast<char*>(d_workspace);
-  const DevParams& p = h->dev;
+  const DevParams& p = cfg.dev;
   const LayoutCfg lc = layout_cfg(p);
   Header hd;
   make_header(n, &hd);
@@ -470,7 +526,7 @@ sift_status launch_batch(sift_handle* h, int32_t n, const float* const* d_images
     for (int lv = (k == 0 ? 0 : 1); lv <= p.s + 2; ++lv) {
       BlurArgs a;
       std::memset(&a, 0, sizeof a);
-      const Taps& t = lv == 0 ? h->init : h->inc[lv - 1];
+      const Taps& t = lv == 0 ? cfg.init : cfg.inc[lv - 1];
       const int cls = blur_class(h->params.tile_rows, &tiles[k * kNumTileH]);
       const int th = tile_h_of(cls);
       a.ws = ws;
@@ -555,43 +611,72 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
   if (workspace_bytes < need)
     return fail(SIFT_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %zu", workspace_bytes, need);
 
-  int first[kMaxParts + 1];
-  int parts = batch_parts(n, h->params.n_streams, first);
+  bool one_sequence = false;
   {
     // stage profiling times one sequence of launches on the caller's stream
     std::lock_guard<std::mutex> lk(g_prof.mu);
-    if (g_prof.on && !g_capturing) parts = 1;
+    one_sequence = g_prof.on && !g_capturing;
   }
-  if (parts == 1)
-    return launch_batch(h, n, d_images, heights, widths, pitches, d_workspace, outs, stream_v);
-  split_parts(h, n, heights, widths, parts, first);
+  const std::vector<Part> parts = plan_parts(h, n, heights, widths, one_sequence);
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+  char* ws = static_cast<char*>(d_workspace);
+  // the images, sizes and outputs of one part, gathered in its order
+  struct Gathered {
+    std::vector<const float*> img;
+    std::vector<int32_t> h, w;
+    std::vector<int64_t> pitch;
+    std::vector<sift_output> out;
+  };
+  auto gather = [&](const Part& pt) {
+    Gathered g;
+    for (int i : pt.idx) {
+      g.img.push_back(d_images[i]);
+      g.h.push_back(heights[i]);
+      g.w.push_back(widths[i]);
+      g.pitch.push_back(pitches[i]);
+      g.out.push_back(outs[i]);
+    }
+    return g;
+  };
+  auto run_part = [&](const Part& pt, char* base, hipStream_t q) {
+    const Gathered g = gather(pt);
+    return launch_batch(h, h->cfg[pt.cfg], (int32_t)pt.idx.size(), g.img.data(), g.h.data(),
+                        g.w.data(), g.pitch.data(), base, g.out.data(), q);
+  };
+  if (parts.size() == 1) return run_part(parts[0], ws, stream);
+  if (one_sequence) {
+    // one stream: the parts one after the other
+    int64_t off = 0;
+    for (const Part& pt : parts) {
+      if ((st = run_part(pt, ws + off, stream)) != SIFT_OK) return st;
+      off += part_bytes(h, pt, heights, widths);
+    }
+    return SIFT_OK;
+  }
   std::call_once(h->streams_once, [h] {
     for (int i = 0; i < kMaxParts && h->streams_status == hipSuccess; ++i)
       h->streams_status = hipStreamCreateWithFlags(&h->part_stream[i], hipStreamNonBlocking);
   });
   if (h->streams_status != hipSuccess) return check_hip(h->streams_status, "sub-batch streams");
-  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+  const int np = (int)parts.size();
   hipEvent_t ev[kMaxParts + 1] = {};
   hipError_t e = hipSuccess;
-  for (int q = 0; q <= parts && e == hipSuccess; ++q)
+  for (int q = 0; q <= np && e == hipSuccess; ++q)
     e = hipEventCreateWithFlags(&ev[q], hipEventDisableTiming);
   // fork: every sub-batch stream waits for the caller's stream
-  if (e == hipSuccess) e = hipEventRecord(ev[parts], stream);
-  for (int q = 0; q < parts && e == hipSuccess; ++q)
-    e = hipStreamWaitEvent(h->part_stream[q], ev[parts], 0);
-  char* ws = static_cast<char*>(d_workspace);
+  if (e == hipSuccess) e = hipEventRecord(ev[np], stream);
+  for (int q = 0; q < np && e == hipSuccess; ++q)
+    e = hipStreamWaitEvent(h->part_stream[q], ev[np], 0);
   int64_t off = 0;
-  for (int q = 0; q < parts && e == hipSuccess && st == SIFT_OK; ++q) {
-    const int lo = first[q], hi = first[q + 1];
-    st = launch_batch(h, hi - lo, d_images + lo, heights + lo, widths + lo, pitches + lo,
-                      ws + off, outs + lo, h->part_stream[q]);
-    off += part_bytes(h, lo, hi, heights, widths);
+  for (int q = 0; q < np && e == hipSuccess && st == SIFT_OK; ++q) {
+    st = run_part(parts[q], ws + off, h->part_stream[q]);
+    off += part_bytes(h, parts[q], heights, widths);
     if (st == SIFT_OK) e = hipEventRecord(ev[q], h->part_stream[q]);
   }
   // join: the caller's stream waits for every sub-batch
-  for (int q = 0; q < parts && e == hipSuccess && st == SIFT_OK; ++q)
+  for (int q = 0; q < np && e == hipSuccess && st == SIFT_OK; ++q)
     e = hipStreamWaitEvent(stream, ev[q], 0);
-  for (int q = 0; q <= parts; ++q)
+  for (int q = 0; q <= np; ++q)
     if (ev[q]) hipEventDestroy(ev[q]);
   if (st != SIFT_OK) return st;
   return check_hip(e, "sub-batch streams");
@@ -613,12 +698,13 @@ sift_status sift_workspace_level(const sift_handle* h, int32_t height, int32_t w
     return fail(SIFT_ERR_INVALID_ARG, "null argument");
   sift_status st = validate_size(h, height, width);
   if (st != SIFT_OK) return st;
-  const int k = octave - h->dev.o0;
-  if (k < 0 || k >= h->dev.n_oct) return fail(SIFT_ERR_INVALID_ARG, "no octave %d", octave);
-  if (level < 0 || level > h->dev.s + 2) return fail(SIFT_ERR_INVALID_ARG, "no level %d", level);
+  const DevParams& d = cfg_for(h, height, width).dev;
+  const int k = octave - d.o0;
+  if (k < 0 || k >= d.n_oct) return fail(SIFT_ERR_INVALID_ARG, "no octave %d", octave);
+  if (level < 0 || level > d.s + 2) return fail(SIFT_ERR_INVALID_ARG, "no level %d", level);
   Header hd;
   make_header(1, &hd);
-  const OctView ov = octave_view(height, width, layout_cfg(h->dev), k);
+  const OctView ov = octave_view(height, width, layout_cfg(d), k);
   *d_level = reinterpret_cast<const float*>(static_cast<const char*>(d_workspace) + hd.bytes +
                                             ov.level0 + (int64_t)level * ov.plane);
   *level_height = ov.h;

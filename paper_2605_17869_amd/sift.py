@@ -39,7 +39,7 @@ class SiftParams(ctypes.Structure):
         ("n_dsp", ctypes.c_int32), ("dsp_scales", ctypes.c_float * MAX_DSP),
         ("rootsift", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
         ("max_candidates", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
-        ("n_streams", ctypes.c_int32),
+        ("n_streams", ctypes.c_int32), ("upsample_max_pixels", ctypes.c_int32),
     ]
 
 

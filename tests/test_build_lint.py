@@ -20,5 +20,6 @@ def test_kernels_have_no_misaligned_scalar_offsets(tmp_path):
     for out, pr in jobs:
         assert pr.wait() == 0
         text = out.read_text()
-        assert "s_load" in text
+        if "__global__" in (build.CSRC / out.name[:-2]).read_text():
+            assert "s_load" in text     # the files with kernels do load arguments
         assert build.smem_misaligned(text) == []

@@ -264,3 +264,31 @@ def test_sub_batches_on_streams_are_bitwise_identical():
             a, b = singles[k], got[k]
             assert digest(a[0], a[1]) == digest(b[0], b[1]), (streams, k)
             assert a[2:] == b[2:], (streams, k)
+
+
+def test_upsample_limit_mixed_batch():
+    """A batch mixing images below and above upsample_max_pixels: each image
+    gives the bits of extracting it alone with the octave structure the
+    policy picks (octave -1 only for the small ones), in any batch order, and
+    matches the oracle under the same policy."""
+    from paper_2605_17869_amd import Extractor
+    sizes = [(97, 129), (300, 410), (130, 75), (280, 260)]
+    limit = 40000
+    imgs = [blobs(900 + k, h, w, 3 * DENSITY) for k, (h, w) in enumerate(sizes)]
+    settings = dict(synth.BASE_SETTINGS, n_octaves=2, upsample=1, upsample_max_pixels=limit)
+    ex = Extractor(settings)
+    batched = extract_batch(ex, imgs)
+    shuffled = extract_batch(ex, imgs[::-1])[::-1]
+    for k, im in enumerate(imgs):
+        small = im.shape[0] * im.shape[1] <= limit
+        alone = extract(Extractor(dict(settings, upsample=1 if small else 0,
+                                       upsample_max_pixels=0)), im)
+        for got in (batched[k], shuffled[k]):
+            assert digest(got[0], got[1]) == digest(alone[0], alone[1]), k
+            assert got[2:] == alone[2:], k
+        assert (min(batched[k][0]["octave"]) == -1) == small
+    p = so.Params.from_settings(settings)
+    for k in (0, 1):
+        ref = oracle.sift(imgs[k], p, keep_octaves=True)
+        kp, desc, nf, nc = batched[k]
+        assert_parity(p, ref, kp, desc, nf, nc)

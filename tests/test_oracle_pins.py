@@ -447,3 +447,20 @@ def test_canonical_order_and_cap():
 def test_image_too_small_raises():
     with pytest.raises(ValueError):
         so.scale_space(np.zeros((40, 40), np.float32), p_default(n_octaves=4))
+
+
+def test_upsample_limit_drops_octave_minus_one_above_the_size():
+    """The VRAM-adaptive policy: with upsample on and a pixel limit, an image
+    above the limit is extracted exactly as with upsample off, one at or below
+    it exactly as with upsample on."""
+    from paper_2605_17869_amd import synth
+    img = synth.blob_image(15, 97, 129, 40)            # 12513 pixels
+    on = oracle.sift(img, p_default(n_octaves=2, upsample=1))
+    off = oracle.sift(img, p_default(n_octaves=2, upsample=0))
+    assert len(on.keypoints) != len(off.keypoints)
+    above = oracle.sift(img, p_default(n_octaves=2, upsample=1, upsample_max_pixels=12512))
+    at = oracle.sift(img, p_default(n_octaves=2, upsample=1, upsample_max_pixels=12513))
+    assert np.array_equal(above.keypoints, off.keypoints)
+    assert np.array_equal(above.descriptors, off.descriptors)
+    assert np.array_equal(at.keypoints, on.keypoints)
+    assert min(above.keypoints["octave"]) == 0 and min(at.keypoints["octave"]) == -1
