@@ -164,6 +164,32 @@ sift_status sift_extract(sift_handle* h, const float* d_image, int32_t height, i
                          int64_t pitch, void* d_workspace, size_t workspace_bytes,
                          const sift_output* out, void* stream);
 
+/*
+ * Extraction without any allocation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same arguments and results as sift_extract (bit-identical
+ * outputs), but the workspace is a static device array inside the library,
+ * SIFT_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, held from module load until the
+ * process ends: enough for a 1600x1066 image with the default settings, or a
+ * 640x480 image with the upsampled octave.  The call allocates nothing (no
+ * hipMalloc/hipFree, no allocating library routine); its first call on a
+ * device looks up that device's array address.  The image, outputs and stream
+ * belong to the current device.  Errors: as sift_extract, plus
+ * WORKSPACE_TOO_SMALL when sift_workspace_size for the image exceeds the
+ * array (sift_last_error() gives both sizes).  Every call on one GPU uses that
+ * GPU's single array and leaves the last call's state in it (nothing in it
+ * needs clearing: each extraction writes every word it reads before reading
+ * it).  Calls whose work overlaps on one GPU (enqueued on different streams,
+ * or from different threads) race on the array; calls enqueued on one stream
+ * run one after another and are safe.
+ */
+#define SIFT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sift_status sift_extract_noalloc(sift_handle* h, const float* d_image, int32_t height,
+                                 int32_t width, int64_t pitch, const sift_output* out,
+                                 void* stream);
+/* SIFT_NOALLOC_SCRATCH_BYTES as built into the library. */
+size_t sift_noalloc_scratch_bytes(void);
+
 /* Workspace bytes for a batch of n images with the given sizes (host arrays). */
 sift_status sift_batch_workspace_size(const sift_handle* h, int32_t n, const int32_t* heights,
                                       const int32_t* widths, size_t* bytes);

@@ -144,6 +144,10 @@ _SIGNATURES = {
                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_float)]),
+    "sift_extract_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                            ctypes.c_int32, ctypes.c_int64,
+                                            ctypes.POINTER(SiftOutput), ctypes.c_void_p]),
+    "sift_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "sift_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sift_last_error": (ctypes.c_char_p, []),
 }
@@ -313,6 +317,24 @@ class Extractor:
                                      ws.numel() * ws.element_size(), ctypes.byref(o),
                                      _stream_handle(stream)), "sift_extract")
         return f
+
+    def extract_noalloc(self, image, out: Features, capacity: int | None = None,
+                        stream=None) -> Features:
+        """``sift_extract_noalloc``: extraction into the library's static
+        device scratch (no workspace argument, nothing allocated here either:
+        ``out`` is the caller's)."""
+        import torch
+        if image.dim() != 2 or image.dtype != torch.float32 or not image.is_cuda:
+            raise ValueError("image must be a 2-D float32 CUDA tensor")
+        if image.stride(1) != 1:
+            raise ValueError("image rows must be contiguous")
+        h, w = image.shape
+        cap = out.keypoints.shape[0] if capacity is None else int(capacity)
+        o = self._output(out, cap)
+        _check(self.lib.sift_extract_noalloc(self.handle, ctypes.c_void_p(image.data_ptr()), h, w,
+                                             image.stride(0), ctypes.byref(o),
+                                             _stream_handle(stream)), "sift_extract_noalloc")
+        return out
 
     def _batch_args(self, images, capacity, outs, workspace):
         import torch
