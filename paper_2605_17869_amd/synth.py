@@ -219,3 +219,29 @@ def workload(number: int, n_images: int | None = None) -> Workload:
     else:
         raise ValueError(f"no workload {number}")
     return wl
+
+
+def descriptor_sets(seed: int, n_a: int, n_b: int, n_common: int, noise: float = 0.05,
+                    dim: int = 128) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Seeded descriptor sets shaped like SIFT output: non-negative unit rows.
+
+    Rows of ``a`` are |N(0, 1)| vectors normalised to unit length.  ``b`` holds
+    ``n_common`` of them (a random subset, in random order), each perturbed by
+    |N(0, noise)| and renormalised, and ``n_b - n_common`` fresh rows.  Returns
+    (a, b, truth) with truth[k] = (row of a, row of b) for the common rows.
+    float32 throughout; no part of matching is computed here."""
+    rng = np.random.default_rng(seed)
+
+    def unit(x):
+        x = np.abs(x)
+        return x / np.linalg.norm(x, axis=1, keepdims=True)
+
+    if not 0 <= n_common <= min(n_a, n_b):
+        raise ValueError("n_common must be in 0..min(n_a, n_b)")
+    a = unit(rng.normal(size=(n_a, dim)))
+    src = rng.permutation(n_a)[:n_common]
+    dst = rng.permutation(n_b)[:n_common]
+    b = unit(rng.normal(size=(n_b, dim)))
+    b[dst] = unit(a[src] + np.abs(rng.normal(0.0, noise, size=(n_common, dim))))
+    truth = np.stack([src, dst], axis=1) if n_common else np.zeros((0, 2), dtype=np.int64)
+    return a.astype(np.float32), b.astype(np.float32), truth.astype(np.int64)
