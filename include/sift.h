@@ -234,6 +234,22 @@ typedef struct {
 sift_status sift_profile_start(void);
 sift_status sift_profile_stop(sift_stage_stat* stats, int32_t max_stats, int32_t* n_stats);
 
+/* The launches recorded so far, one entry each in enqueue order (at most
+ * max_out; waits for their events; recording continues): stage name, a
+ * detail label (blur: "o<octave> l<level> R<radius>"), event time, algorithmic
+ * bytes and the fused multiply-adds the launch must issue (blur: two passes
+ * of 2R + 1 taps per output pixel; 0 where not counted).  Call between
+ * sift_profile_start and sift_profile_stop. */
+typedef struct {
+  char stage[32];
+  char label[32];
+  double ms;
+  double bytes;
+  double fmas;
+} sift_launch_stat;
+
+sift_status sift_profile_launches(sift_launch_stat* out, int32_t max_out, int32_t* n_out);
+
 /* Static text for a status code. */
 /*
  * Replayable batches (HIP graphs).  For a batch whose shapes and buffers
@@ -343,6 +359,63 @@ sift_status sift_server_poll(sift_server* s, uint64_t ticket, int32_t* done, dou
 sift_status sift_server_wait(sift_server* s, uint64_t ticket, double* latency_ms);
 sift_status sift_server_get_stats(sift_server* s, sift_server_stats* stats);
 sift_status sift_server_destroy(sift_server* s);
+
+/*
+ * Descriptor matching: the symmetric ratio test of the paper's matching step
+ * (Section 3.4, "Descriptor Matching", backend (1): a similarity matrix from
+ * fp16 descriptors on the matrix cores, a nearest-neighbour ratio test and
+ * mutual-consistency filtering), for many pairs of descriptor sets in one
+ * launch sequence.
+ *
+ * For a pair (a, b): s_ij = <fp16(a_i), fp16(b_j)>, the descriptors rounded
+ * to fp16 (nearest even) and the products accumulated in fp32 by the matrix
+ * cores in an order fixed by the code (run-to-run bit-identical).  With
+ * D = max(2 - 2 s, 0) (squared distance of unit vectors) a_i's nearest
+ * neighbour j is the largest s_ij (smallest j among equals), D1 its distance,
+ * D2 the second-nearest's (4 if b has one row); likewise b_j's nearest in a.
+ * The pair (i, j) is kept when i and j are each other's nearest neighbours
+ * and D1 < fp32(ratio^2) * D2 holds both ways (taken in fp32).  Matches come
+ * in ascending query index.
+ *
+ * Each sift_match_pair names device memory the caller owns: desc_a
+ * [cap_a][128] and desc_b [cap_b][128] fp32 row-major (sift_output's
+ * descriptor layout); count_a / count_b point at the number of rows in use
+ * (clamped to the cap; e.g. sift_output.count, so extraction and matching
+ * chain on the device without the host reading counts), or are NULL for
+ * cap_a / cap_b rows; matches [capacity]; *n_matches receives the number
+ * written (min(kept, capacity)), *n_found (may be NULL) the number kept.
+ * Caps are host values that size the launch; 0 <= cap <= 65536.
+ * sift_match_workspace_size gives the workspace for the pairs (host array);
+ * sift_match_batch enqueues the matching on `stream` (no allocation, copy
+ * or synchronisation).  Errors: INVALID_ARG for null pointers, caps out of
+ * range, ratio not in (0, 1], WORKSPACE_TOO_SMALL; HIP for launch failures.
+ */
+typedef struct {
+  int32_t query;        /* row of desc_a */
+  int32_t train;        /* row of desc_b */
+  float similarity;     /* s_ij as accumulated */
+  float distance;       /* sqrt(max(2 - 2 s_ij, 0)) */
+} sift_match;
+
+typedef struct {
+  const float* desc_a;
+  const int32_t* count_a;
+  int32_t cap_a;
+  const float* desc_b;
+  const int32_t* count_b;
+  int32_t cap_b;
+  sift_match* matches;
+  int32_t* n_matches;
+  int32_t* n_found;
+  int32_t capacity;
+} sift_match_pair;
+
+#define SIFT_MATCH_MAX_ROWS 65536
+#define SIFT_MATCH_MAX_PAIRS 4096
+
+sift_status sift_match_workspace_size(int32_t n, const sift_match_pair* pairs, size_t* bytes);
+sift_status sift_match_batch(int32_t n, const sift_match_pair* pairs, float ratio,
+                             void* d_workspace, size_t workspace_bytes, void* stream);
 
 const char* sift_status_string(sift_status st);
 /* Detail of the last error on the calling thread ("" if none). */

@@ -3,5 +3,6 @@
 The extraction path is the HIP library ``libsift_mi355x.so`` behind the C ABI
 of ``include/sift.h``; :mod:`.sift` is its Python binding.
 """
-from .sift import (DESC_DIM, KEYPOINT_DTYPE, Extractor, Features, Server, SiftError,  # noqa: F401
-                   load_library, make_params, profile_start, profile_stop)
+from .sift import (DESC_DIM, KEYPOINT_DTYPE, MATCH_DTYPE, Extractor, Features, Matches,  # noqa: F401
+                   Server, SiftError, load_library, make_params, match, match_batch,
+                   profile_launches, profile_start, profile_stop)

@@ -51,6 +51,11 @@ class SiftOutput(ctypes.Structure):
     ]
 
 
+class SiftLaunchStat(ctypes.Structure):
+    _fields_ = [("stage", ctypes.c_char * 32), ("label", ctypes.c_char * 32),
+                ("ms", ctypes.c_double), ("bytes", ctypes.c_double), ("fmas", ctypes.c_double)]
+
+
 class SiftStageStat(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32),
                 ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
@@ -68,6 +73,17 @@ class SiftServerStats(ctypes.Structure):
                 ("batches", ctypes.c_int64), ("peak_arena", ctypes.c_int64),
                 ("peak_inflight", ctypes.c_int64), ("largest_batch", ctypes.c_int64),
                 ("overlapped_batches", ctypes.c_int64)]
+
+
+class SiftMatchPair(ctypes.Structure):
+    _fields_ = [("desc_a", ctypes.c_void_p), ("count_a", ctypes.c_void_p), ("cap_a", ctypes.c_int32),
+                ("desc_b", ctypes.c_void_p), ("count_b", ctypes.c_void_p), ("cap_b", ctypes.c_int32),
+                ("matches", ctypes.c_void_p), ("n_matches", ctypes.c_void_p),
+                ("n_found", ctypes.c_void_p), ("capacity", ctypes.c_int32)]
+
+
+MATCH_DTYPE = np.dtype([("query", "<i4"), ("train", "<i4"), ("similarity", "<f4"),
+                        ("distance", "<f4")])
 
 
 # name -> (restype, argtypes)
@@ -101,6 +117,8 @@ _SIGNATURES = {
     "sift_profile_start": (ctypes.c_int, []),
     "sift_profile_stop": (ctypes.c_int, [ctypes.POINTER(SiftStageStat), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),
+    "sift_profile_launches": (ctypes.c_int, [ctypes.POINTER(SiftLaunchStat), ctypes.c_int32,
+                                             ctypes.POINTER(ctypes.c_int32)]),
     "sift_server_create": (ctypes.c_int, [ctypes.POINTER(SiftParams), ctypes.c_void_p,
                                           ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ctypes.c_void_p)]),
@@ -148,6 +166,11 @@ _SIGNATURES = {
                                             ctypes.c_int32, ctypes.c_int64,
                                             ctypes.POINTER(SiftOutput), ctypes.c_void_p]),
     "sift_noalloc_scratch_bytes": (ctypes.c_size_t, []),
+    "sift_match_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(SiftMatchPair),
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "sift_match_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(SiftMatchPair),
+                                        ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t,
+                                        ctypes.c_void_p]),
     "sift_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sift_last_error": (ctypes.c_char_p, []),
 }
@@ -236,6 +259,16 @@ def profile_stop() -> dict:
     _check(load_library().sift_profile_stop(arr, 16, ctypes.byref(n)), "sift_profile_stop")
     return {arr[i].name.decode(): (arr[i].launches, arr[i].ms, arr[i].bytes)
             for i in range(n.value)}
+
+
+def profile_launches(max_launches: int = 4096) -> list:
+    """Recorded launches so far: [(stage, label, ms, bytes, fmas)] in enqueue order."""
+    arr = (SiftLaunchStat * max_launches)()
+    n = ctypes.c_int32()
+    _check(load_library().sift_profile_launches(arr, max_launches, ctypes.byref(n)),
+           "sift_profile_launches")
+    return [(arr[i].stage.decode(), arr[i].label.decode(), arr[i].ms, arr[i].bytes, arr[i].fmas)
+            for i in range(n.value)]
 
 
 def _stream_handle(stream) -> ctypes.c_void_p:
@@ -544,3 +577,74 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+@dataclass
+class Matches:
+    """Device-resident matches of one pair (torch tensors on the GPU)."""
+    records: object        # int32 [capacity, 4]: sift_match records
+    counters: object       # int32 [2]: n_matches, n_found
+
+    def host(self):
+        """(matches as a MATCH_DTYPE array, n_found)."""
+        cnt = self.counters.cpu().numpy()
+        n = int(cnt[0])
+        rec = self.records[:n].cpu().numpy().copy().view(MATCH_DTYPE).reshape(-1)
+        return rec, int(cnt[1])
+
+
+def _desc_arg(desc, count):
+    import torch
+    if desc.dim() != 2 or desc.shape[1] != DESC_DIM or desc.dtype != torch.float32 \
+            or not desc.is_cuda or not desc.is_contiguous():
+        raise ValueError("descriptors must be a contiguous float32 CUDA tensor [rows, 128]")
+    cptr = None
+    if count is not None:
+        if count.dtype != torch.int32 or not count.is_cuda:
+            raise ValueError("count must be an int32 CUDA tensor")
+        cptr = count.data_ptr()
+    return desc.data_ptr() if desc.shape[0] else None, cptr, int(desc.shape[0])
+
+
+def match_batch(pairs, ratio: float = 0.8, workspace=None, stream=None, outs=None) -> list:
+    """``sift_match_batch`` over pairs of (desc_a, count_a, desc_b, count_b):
+    descriptors are float32 CUDA tensors [cap, 128]; a count is a one-element
+    int32 CUDA tensor holding the rows in use (e.g. ``Features.counters[0:1]``)
+    or None for all rows.  Returns one ``Matches`` per pair (enqueued on the
+    current or given stream); ``outs`` reuses the ``Matches`` of an earlier call
+    on pairs of the same sizes."""
+    import torch
+    lib = load_library()
+    n = len(pairs)
+    arr = (SiftMatchPair * n)()
+    reuse = outs is not None
+    outs = list(outs) if reuse else []
+    for i, (da, ca, db, cb) in enumerate(pairs):
+        pa, qa, na = _desc_arg(da, ca)
+        pb, qb, nb = _desc_arg(db, cb)
+        if reuse:
+            m = outs[i]
+            cap = int(m.records.shape[0])
+        else:
+            cap = max(min(na, nb), 1)
+            m = Matches(torch.empty((cap, 4), dtype=torch.int32, device="cuda"),
+                        torch.zeros(2, dtype=torch.int32, device="cuda"))
+            outs.append(m)
+        base = m.counters.data_ptr()
+        arr[i] = SiftMatchPair(pa, qa, na, pb, qb, nb, m.records.data_ptr(), base, base + 4, cap)
+    need = ctypes.c_size_t()
+    _check(lib.sift_match_workspace_size(n, arr, ctypes.byref(need)), "sift_match_workspace_size")
+    ws = workspace
+    if ws is None or ws.numel() * ws.element_size() < need.value:
+        ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device="cuda")
+    _check(lib.sift_match_batch(n, arr, ctypes.c_float(ratio), ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel() * ws.element_size(), _stream_handle(stream)),
+           "sift_match_batch")
+    for m in outs:
+        m._ws = ws   # keep the workspace alive with the results
+    return outs
+
+
+def match(desc_a, desc_b, ratio: float = 0.8, count_a=None, count_b=None, stream=None) -> Matches:
+    """One pair: see ``match_batch``."""
+    return match_batch([(desc_a, count_a, desc_b, count_b)], ratio=ratio, stream=stream)[0]
