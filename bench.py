@@ -85,6 +85,62 @@ def make_images(wl_no: int, n: int):
     return wl, imgs
 
 
+FMA_PEAK_T = 256 * 64 * 2.4e9 / 1e12   # non-packed fp32 FMA issue: CUs x lanes x clock (T FMA/s)
+FP16_MFMA_PEAK_TFLOPS = 2500.0         # dense fp16 matrix peak, TFLOP/s
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _oracle_worker_init():
+    # one BLAS/OpenMP thread per worker process
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _oracle_one(args):
+    wl_no, n, k = args
+    import oracle
+    from oracle import sift_oracle as so
+    wl = synth.workload(wl_no, n)
+    img = wl.image(k)
+    p = so.Params.from_settings(wl.settings)
+    t = time.perf_counter()
+    oracle.sift(img, p)
+    return time.perf_counter() - t
+
+
+def pixel_octaves(sizes, upsample: int, n_oct: int) -> int:
+    """Pixels summed over every octave of every image (octave sizes halve,
+    rounding up; the first octave is 2H x 2W when upsampling)."""
+    tot = 0
+    for h, w in sizes:
+        hh, ww = (2 * h, 2 * w) if upsample else (h, w)
+        for _ in range(n_oct):
+            tot += hh * ww
+            hh, ww = (hh + 1) // 2, (ww + 1) // 2
+    return tot
+
+
 def digest(kp, desc) -> str:
     h = hashlib.sha256()
     h.update(np.ascontiguousarray(kp).tobytes())
@@ -92,22 +148,62 @@ def digest(kp, desc) -> str:
     return h.hexdigest()
 
 
-def serve_bench(args):
-    """Serving: requests arrive as a Poisson process at fractions of the
-    batched saturation rate; the continuous-batching server and the plain
-    one-at-a-time path (max_batch 1, one in flight) serve the same arrivals.
-    Latency is submit to observed completion, measured by the server."""
+def match_bench(n_pairs: int, n_a: int, n_b: int, reps: int = 20):
+    """Symmetric ratio-test matching of n_pairs seeded descriptor-set pairs
+    (n_a x n_b rows each) in one sift_match_batch call: pairs/s, and the
+    similarity work against the dense fp16 matrix peak."""
     import torch
     import paper_2605_17869_amd as sm
-    wl = synth.workload(4, args.unique_images)
+    sets = [synth.descriptor_sets(900_000 + k, n_a, n_b, (3 * min(n_a, n_b)) // 4, 0.1)
+            for k in range(n_pairs)]
+    dev = torch.device("cuda:0")
+    pairs = [(torch.from_numpy(a).to(dev), None, torch.from_numpy(b).to(dev), None)
+             for a, b, _ in sets]
+    stream = torch.cuda.current_stream()
+    outs = sm.match_batch(pairs, stream=stream)
+    ws = outs[0]._ws
+    first = [m.host() for m in outs]
+    for _ in range(3):
+        sm.match_batch(pairs, workspace=ws, stream=stream, outs=outs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        sm.match_batch(pairs, workspace=ws, stream=stream, outs=outs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    again = [m.host() for m in outs]
+    same = all(a[0].tobytes() == b[0].tobytes() for a, b in zip(first, again))
+    flops = 2.0 * 128 * n_a * n_b * n_pairs
+    kept = float(np.mean([len(m[0]) for m in again]))
+    return {"pairs": n_pairs, "rows_per_set": [n_a, n_b], "ms_per_call": round(ms, 4),
+            "pairs_per_s": round(n_pairs / (ms * 1e-3), 1),
+            "similarity_tflops": round(flops / (ms * 1e-3) / 1e12, 2),
+            "frac_fp16_mfma_peak": round(flops / (ms * 1e-3) / 1e12 / FP16_MFMA_PEAK_TFLOPS, 4),
+            "mean_matches_per_pair": round(kept, 1), "bitwise_identical_reruns": same,
+            "data": "seeded descriptor sets: 3/4 of the rows noisy copies, the rest fresh"}
+
+
+def serve_points(unique_images: int, requests: int, warmup_requests: int, fractions,
+                 one_at_a_time: bool):
+    """Serving: requests arrive as a Poisson process at fractions of the
+    batched saturation rate; the continuous-batching server (and, if asked,
+    the plain one-at-a-time path: max_batch 1, one in flight) serve the same
+    arrivals.  Latency is from entry into submit to observed completion,
+    measured by the server.  Returns (workload, images, saturation,
+    one-at-a-time saturation, points)."""
+    import torch
+    import paper_2605_17869_amd as sm
+    wl = synth.workload(4, unique_images)
     t0 = time.time()
-    _, imgs = make_images(4, args.unique_images)
+    _, imgs = make_images(4, unique_images)
     print(f"[serve] generated {len(imgs)} images in {time.time() - t0:.1f}s", file=sys.stderr,
           flush=True)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     d_imgs = [torch.from_numpy(im).to(dev) for im in imgs]
-    n_req = args.requests + args.warmup_requests
+    n_req = requests + warmup_requests
     order = [k % len(d_imgs) for k in range(n_req)]
     settings = dict(wl.settings)
     cap = settings["max_keypoints"]
@@ -119,38 +215,56 @@ def serve_bench(args):
     def run(arrivals, max_batch, max_inflight):
         srv = sm.Server(settings, arena_bytes=arena, max_batch=max_batch,
                         max_inflight=max_inflight)
-        tickets = []
+        tickets, late = [], []
         start = time.perf_counter()
         for i in range(n_req):
             if arrivals is not None:
                 while time.perf_counter() - start < arrivals[i]:
                     pass
+                # a request submitted after its scheduled arrival (the client
+                # was held up) is charged the delay as well
+                late.append(max(0.0, time.perf_counter() - start - arrivals[i]) * 1e3)
+            else:
+                late.append(0.0)
             tickets.append(srv.submit(d_imgs[order[i]], out=feats[i]))
-        lat = [srv.wait(t)[0] for t in tickets]
+        lat = [srv.wait(t)[0] + d for t, d in zip(tickets, late)]
         wall = time.perf_counter() - start
         stats = srv.stats()
         srv.close()
-        meas = np.array(lat[args.warmup_requests:])
+        meas = np.array(lat[warmup_requests:])
         return dict(p50_ms=round(float(np.percentile(meas, 50)), 3),
                     p99_ms=round(float(np.percentile(meas, 99)), 3),
                     images_per_s=round(n_req / wall, 2),
-                    batches=stats["batches"], mean_batch=round(n_req / stats["batches"], 2))
+                    batches=stats["batches"], mean_batch=round(n_req / stats["batches"], 2),
+                    largest_batch=stats["largest_batch"],
+                    overlapped_batches=stats["overlapped_batches"])
 
     run(None, 64, 2)   # warm-up
     sat = run(None, 64, 2)
     sat_rate = sat["images_per_s"]
     print(f"[serve] saturation {sat_rate} images/s {sat}", file=sys.stderr, flush=True)
-    one = run(None, 1, 1)
-    print(f"[serve] one-at-a-time saturation {one}", file=sys.stderr, flush=True)
+    one = run(None, 1, 1) if one_at_a_time else None
+    if one:
+        print(f"[serve] one-at-a-time saturation {one}", file=sys.stderr, flush=True)
     points = []
-    for k, f in enumerate(float(x) for x in args.qps_fractions.split(",")):
+    for k, f in enumerate(fractions):
         qps = f * sat_rate
         arr = synth.poisson_arrivals(synth.workload_seed(4, 500_000 + k), n_req, qps)
         batched = run(arr, 64, 2)
-        plain = run(arr, 1, 1)
+        plain = run(arr, 1, 1) if one_at_a_time else None
         points.append(dict(qps=round(qps, 1), fraction=f, batched=batched, one_at_a_time=plain))
         print(f"[serve] qps {qps:.1f}: batched {batched} one-at-a-time {plain}", file=sys.stderr,
               flush=True)
+    return wl, imgs, sat, one, points
+
+
+def serve_bench(args):
+    """Full serving sweep as its own JSON line (``--serve``)."""
+    fr = [float(x) for x in args.qps_fractions.split(",")]
+    wl, imgs, sat, one, points = serve_points(args.unique_images, args.requests,
+                                              args.warmup_requests, fr, True)
+    sat_rate = sat["images_per_s"]
+    arena = 24 << 30
     mpix = float(np.mean([h * w for h, w in wl.sizes])) / 1e6
     line = {
         "metric": "served images/s and p50/p99 latency (continuous batching, Poisson arrivals)",
@@ -190,6 +304,9 @@ def main():
     ap.add_argument("--unique-images", type=int, default=160,
                     help="serving: distinct images, cycled over the requests")
     ap.add_argument("--qps-fractions", default="0.25,0.5,0.75,0.9")
+    ap.add_argument("--no-serve-point", action="store_true",
+                    help="skip the serving point (saturation and p50/p99 at half of it)")
+    ap.add_argument("--no-match", action="store_true", help="skip the matcher measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -214,7 +331,18 @@ def main():
     n = len(imgs)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    d_imgs = [torch.from_numpy(im).to(dev) for im in imgs]
+    # host-to-device copy of the batch from pinned buffers, timed on its own
+    # (the extraction timings below start from device-resident images)
+    pinned = [torch.from_numpy(im).pin_memory() for im in imgs]
+    d_imgs = [torch.empty(im.shape, dtype=torch.float32, device=dev) for im in imgs]
+    torch.cuda.synchronize()
+    h0 = time.perf_counter()
+    for d, h in zip(d_imgs, pinned):
+        d.copy_(h, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d_s = time.perf_counter() - h0
+    h2d_bytes = sum(im.nbytes for im in imgs)
+    del pinned
     sizes = [tuple(im.shape) for im in imgs]
     stream = torch.cuda.current_stream()
     tune = None
@@ -296,6 +424,7 @@ def main():
         for _ in range(2):
             batch_step()
         torch.cuda.synchronize()
+        launches_rec = sm.profile_launches()
         stats = sm.profile_stop()
         for name, (launches, sms, sbytes) in stats.items():
             stages[name] = dict(launches=launches // 2, ms=round(sms / 2, 4),
@@ -310,24 +439,74 @@ def main():
                         "avg_launch_us": round(1e3 * bms / launches, 2),
                         "bytes_per_launch": round(bbytes / launches),
                         "kernel_source_sha256": kernel_source_hash()}
+            # every blur launch of the second profiled step: HBM and FMA-issue fractions
+            blur_recs = [r for r in launches_rec if r[0] == "blur"]
+            per = []
+            for _, label, lms, lbytes, lfmas in blur_recs[len(blur_recs) // 2:]:
+                sec = lms * 1e-3
+                per.append({"launch": label, "us": round(lms * 1e3, 1),
+                            "gb": round(lbytes / 1e9, 4), "gfma": round(lfmas / 1e9, 3),
+                            "frac_hbm": round(lbytes / sec / 1e9 / HBM_PEAK_GBS, 3),
+                            "frac_fma_nonpacked": round(lfmas / sec / (FMA_PEAK_T * 1e12), 3)})
+            roofline["per_launch"] = per
+            roofline["fma_peak_nonpacked_tfma_s"] = round(FMA_PEAK_T, 2)
+            # pyramid + DoG + extrema judged on time under a stored-pyramid model of
+            # 88 bytes per pixel-octave (5 levels read and written, 5 DoG planes
+            # written and read back, the base read and written)
+            det = stats.get("detect")
+            if det:
+                n_oct = wl.settings["n_octaves"] + wl.settings["upsample"]
+                model = 88.0 * pixel_octaves(sizes, wl.settings["upsample"], n_oct)
+                t_ms = (bms + det[1]) / 2
+                roofline["pyramid_time_equivalent"] = {
+                    "model_bytes_per_step": round(model), "blur_plus_detect_ms": round(t_ms, 4),
+                    "gbs": round(model / (t_ms * 1e-3) / 1e9, 1),
+                    "frac": round(model / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         print(f"[bench] stages: {json.dumps(stages)}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
-        # the oracle as it stands, single-threaded, on the first images of the
-        # batch until about 10 s of work (at least one image)
-        import oracle
-        from oracle import sift_oracle as so
-        p = so.Params.from_settings(wl.settings)
+        # the oracle as it stands.  (i) one process, one BLAS thread, on the
+        # first images of the batch until about 8 s of work; (ii) a pool of one
+        # process per usable core (at most 16, the host share of one GPU),
+        # one image each, wall time of the whole pool
+        _oracle_worker_init()
         done, dt = 0, 0.0
-        while done < n and (done == 0 or dt < 10.0):
-            t = time.perf_counter()
-            oracle.sift(imgs[done], p)
-            dt += time.perf_counter() - t
+        while done < n and (done == 0 or dt < 8.0):
+            dt += _oracle_one((args.workload, args.images, done))
             done += 1
-        cpu = {"value": round(done / dt, 5), "unit": "images/s", "cores": 1, "kind": "oracle",
-               "sample": f"the first {done} of the {n} images, full pipeline, {dt:.1f} s "
-                         f"single-threaded FP64 NumPy"}
+        single = round(done / dt, 5)
+        workers = max(1, min(16, usable_cores(), n))
+        t = time.perf_counter()
+        with ProcessPoolExecutor(max_workers=workers, initializer=_oracle_worker_init) as pool:
+            per_img = list(pool.map(_oracle_one, [(args.workload, args.images, k)
+                                                  for k in range(workers)]))
+        wall_pool = time.perf_counter() - t
+        cpu = {"value": round(workers / wall_pool, 5), "unit": "images/s", "cores": workers,
+               "kind": "oracle",
+               "sample": f"pool of {workers} single-threaded FP64 NumPy processes, one of the "
+                         f"first {workers} images each, full pipeline, {wall_pool:.1f} s wall",
+               "cpu_model": cpu_model(), "nproc": os.cpu_count(), "usable_cores": usable_cores(),
+               "single_process": {"images_per_s": single, "threads": 1,
+                                  "sample": f"the first {done} images, {dt:.1f} s"},
+               "pool_mean_s_per_image": round(float(np.mean(per_img)), 2)}
+        print(f"[bench] cpu baseline: {cpu}", file=sys.stderr, flush=True)
+
+    serving = None
+    if not args.no_serve_point:
+        del ws
+        torch.cuda.empty_cache()
+        swl, simgs, sat, _, pts = serve_points(64, 2000, 200, [0.5], False)
+        serving = {"workload": swl.name, "unique_images": len(simgs), "requests": 2000,
+                   "warmup_requests": 200, "max_batch": 64, "max_inflight": 2,
+                   "saturation_images_per_s": sat["images_per_s"],
+                   "at_half_saturation": pts[0]["batched"], "qps": pts[0]["qps"],
+                   "latency": "entry into submit (or the scheduled arrival, if later) to "
+                              "observed completion"}
+
+    matching = None
+    if not args.no_match:
+        matching = match_bench(32, 2000, 2000)
 
     mpix = sum(h * w for h, w in sizes) / 1e6
     n_kp = int(sum(len(b[0]) for b in batch_host))
@@ -362,6 +541,12 @@ def main():
         "stages": stages,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "h2d": {"ms": round(h2d_s * 1e3, 2), "bytes": h2d_bytes,
+                "gbs": round(h2d_bytes / h2d_s / 1e9, 2),
+                "images_per_s_with_h2d": round(n / (ms * 1e-3 + h2d_s), 2),
+                "note": "pinned host buffers, one copy per image, before timing; not in value"},
+        "serving": serving,
+        "matching": matching,
     }
     print(json.dumps(line), flush=True)
 

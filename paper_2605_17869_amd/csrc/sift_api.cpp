@@ -214,6 +214,8 @@ const char* const kStageNames[kStCount] = {"setup", "blur", "detect", "compact",
 struct ProfRecord {
   int stage;
   double bytes;
+  double fmas;            // fused multiply-adds the launch must issue (0: not counted)
+  char label[32];         // launch detail, e.g. "o-1 l2 R7"
   hipEvent_t a, b;
 };
 
@@ -238,13 +240,16 @@ hipEvent_t prof_event() {
 }
 
 // Opens a stage record (no-op when recording is off); close with prof_end.
-int prof_begin(int stage, double bytes, hipStream_t stream) {
+int prof_begin(int stage, double bytes, hipStream_t stream, const char* label = "",
+               double fmas = 0.0) {
   if (g_capturing) return -1;
   std::lock_guard<std::mutex> lk(g_prof.mu);
   if (!g_prof.on) return -1;
   ProfRecord r;
   r.stage = stage;
   r.bytes = bytes;
+  r.fmas = fmas;
+  std::snprintf(r.label, sizeof r.label, "%s", label);
   r.a = prof_event();
   r.b = prof_event();
   if (!r.a || !r.b) return -1;
@@ -546,7 +551,10 @@ sift_status launch_batch(const sift_handle* h, const Config& cfg, int32_t n,
       double bytes = 8.0 * pixels[k];
       if (lv == 0 && p.upsample) bytes = 4.0 * pixels[k] + 4.0 * input_px;
       if (a.mode == kSrcDown) bytes += 4.0 * pixels[k];
-      prec = prof_begin(kStBlur, bytes, stream);
+      char label[32];
+      std::snprintf(label, sizeof label, "o%d l%d R%d", k + p.o0, lv, t.radius);
+      // a vertical and a horizontal pass of 2R + 1 taps per output pixel
+      prec = prof_begin(kStBlur, bytes, stream, label, 2.0 * (2 * t.radius + 1) * pixels[k]);
       const int grid = (int)((tiles[k * kNumTileH + cls] + kXcds - 1) / kXcds * kXcds);
       if ((st = check_hip(launch_blur(a, t.radius, grid, stream), "blur")) != SIFT_OK) return st;
       prof_end(prec, stream);
@@ -717,6 +725,30 @@ sift_status sift_profile_start(void) {
   std::lock_guard<std::mutex> lk(g_prof.mu);
   g_prof.on = true;
   return SIFT_OK;
+}
+
+sift_status sift_profile_launches(sift_launch_stat* out, int32_t max_out, int32_t* n_out) {
+  if (!out || !n_out || max_out < 0) return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  std::lock_guard<std::mutex> lk(g_prof.mu);
+  if (!g_prof.on) return fail(SIFT_ERR_INVALID_ARG, "profiling was not started");
+  sift_status st = SIFT_OK;
+  int k = 0;
+  for (ProfRecord& r : g_prof.recs) {
+    if (k >= max_out) break;
+    float ms = 0.0f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e != hipSuccess && st == SIFT_OK) st = check_hip(e, "profile events");
+    sift_launch_stat& o = out[k++];
+    std::memset(&o, 0, sizeof o);
+    std::snprintf(o.stage, sizeof o.stage, "%s", kStageNames[r.stage]);
+    std::snprintf(o.label, sizeof o.label, "%s", r.label);
+    o.ms = ms;
+    o.bytes = r.bytes;
+    o.fmas = r.fmas;
+  }
+  *n_out = k;
+  return st;
 }
 
 sift_status sift_profile_stop(sift_stage_stat* stats, int32_t max_stats, int32_t* n_stats) {

@@ -1,13 +1,16 @@
 """Summaries of rocprofv3 result databases (SQLite) as short text.
 
     python -m paper_2605_17869_amd.rocprof_summary trace DB [--group PREFIX ...]
+    python -m paper_2605_17869_amd.rocprof_summary dispatches DB FIRST COUNT
     python -m paper_2605_17869_amd.rocprof_summary counters DB COUNTER [--group PREFIX ...]
     python -m paper_2605_17869_amd.rocprof_summary calibrate DB COUNTER KERNEL BYTES_PER_DISPATCH
     python -m paper_2605_17869_amd.rocprof_summary traffic FETCH_DB WRITE_DB CAL_FETCH_DB \
         CAL_WRITE_DB CAL_KERNEL CAL_BYTES PREFIX
 
 ``trace`` prints per-kernel calls, total and average duration (from a
-``--kernel-trace`` run); ``counters`` prints the per-dispatch average of one
+``--kernel-trace`` run); ``dispatches`` lists COUNT consecutive dispatches
+from the FIRST-th (0-based, in start order) with duration, grid, register
+and LDS use, e.g. one launch sequence of a batch; ``counters`` prints the per-dispatch average of one
 counter per kernel (from a ``--pmc`` run); ``calibrate`` prints the ratio of a
 known per-dispatch byte count to what the counter reports for a plain copy
 kernel.  ``traffic`` turns FETCH_SIZE and WRITE_SIZE of the kernels whose
@@ -55,7 +58,7 @@ def grouped(items: "OrderedDict", groups) -> "OrderedDict":
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["trace", "counters", "calibrate", "traffic"])
+    ap.add_argument("mode", choices=["trace", "dispatches", "counters", "calibrate", "traffic"])
     ap.add_argument("db")
     ap.add_argument("rest", nargs="*")
     ap.add_argument("--group", action="append", default=[])
@@ -71,6 +74,16 @@ def main(argv=None):
         print(f"{'kernel':60s} {'calls':>6s} {'total_us':>12s} {'avg_us':>10s} {'pct':>6s}")
         for k, c, d in rows:
             print(f"{k[:60]:60s} {c:6d} {d:12.1f} {d / c:10.2f} {100 * d / total:6.2f}")
+    elif a.mode == "dispatches":
+        first, count = int(a.rest[0]), int(a.rest[1])
+        con = sqlite3.connect(a.db)
+        rows = con.execute(
+            "select name, duration, grid_x, workgroup_x, vgpr_count, accum_vgpr_count, lds_size "
+            "from kernels order by start limit ? offset ?", (count, first)).fetchall()
+        print(f"{'kernel':44s} {'us':>9s} {'groups':>8s} {'wg':>4s} {'vgpr':>5s} {'agpr':>5s} {'lds':>6s}")
+        for name, dur, gx, wx, vg, ag, lds in rows:
+            groups = gx // max(wx, 1)
+            print(f"{_short(name)[:44]:44s} {dur / 1000.0:9.1f} {groups:8d} {wx:4d} {vg:5d} {ag:5d} {lds:6d}")
     elif a.mode == "counters":
         counter = a.rest[0]
         v = counter_values(a.db, counter)
