@@ -273,6 +273,35 @@ sift_status sift_graph_launch(sift_graph* g, void* stream);
 sift_status sift_graph_destroy(sift_graph* g);
 
 /*
+ * Size buckets (replay for images that vary in size).  A bucket is a graph of
+ * the launch sequence for up to n_slots images of at most max_height x
+ * max_width each, recorded once with grids that cover every slot at the
+ * largest size.  sift_bucket_launch writes the image table for the n images
+ * given (their own sizes, host arrays as sift_extract_batch takes them) with a
+ * few setup launches on `stream` and replays the graph there; the kernels read
+ * each image's size from the table and surplus work-groups exit at once, so
+ * each image's results are bit-identical to sift_extract on it.  Slots past n
+ * stay empty.  Every image of a launch must take the same octave structure as
+ * the bucket's largest size (with upsample_max_pixels, both sides of the
+ * limit need their own buckets).  The workspace (sift_bucket_workspace_size,
+ * 256-byte aligned) belongs to the bucket; a bucket serves one launch at a
+ * time, and the handle must outlive it.  Errors: INVALID_ARG for sizes beyond
+ * the bucket, too many images, or a different octave structure;
+ * WORKSPACE_TOO_SMALL; HIP.
+ */
+typedef struct sift_bucket sift_bucket;
+
+sift_status sift_bucket_workspace_size(const sift_handle* h, int32_t n_slots, int32_t max_height,
+                                       int32_t max_width, size_t* bytes);
+sift_status sift_bucket_create(sift_handle* h, int32_t n_slots, int32_t max_height,
+                               int32_t max_width, void* d_workspace, size_t workspace_bytes,
+                               sift_bucket** out);
+sift_status sift_bucket_launch(sift_bucket* b, int32_t n, const float* const* d_images,
+                               const int32_t* heights, const int32_t* widths,
+                               const int64_t* pitches, const sift_output* outs, void* stream);
+sift_status sift_bucket_destroy(sift_bucket* b);
+
+/*
  * Tuning.  sift_autotune_batch times sift_extract_batch on the given batch
  * for every cap on the blur chunk height (64, 128, 256, 512 rows; all give
  * bit-identical results) and returns the fastest in *best_tile_rows and the mean time of

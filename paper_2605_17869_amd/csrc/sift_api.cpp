@@ -464,15 +464,32 @@ sift_status sift_workspace_size(const sift_handle* h, int32_t height, int32_t wi
 
 namespace {
 
-// The launch sequence of one (sub-)batch on `stream`; arguments already checked.
-sift_status launch_batch(const sift_handle* h, const Config& cfg, int32_t n,
-                         const float* const* d_images, const int32_t* heights,
-                         const int32_t* widths, const int64_t* pitches, void* d_workspace,
-                         const sift_output* outs, hipStream_t stream) {
-  sift_status st = SIFT_OK;
-  char* ws = static_cast<char*>(d_workspace);
-  const DevParams& p = cfg.dev;
-  const LayoutCfg lc = layout_cfg(p);
+// Grid sizing of one launch sequence: work items summed over the images it
+// covers (their own sizes, or a bucket's largest size for every slot).
+struct Plan {
+  std::vector<int64_t> tiles;   // blur strips x chunks, [octave * kNumTileH + chunk class]
+  std::vector<int64_t> pixels;  // pixels per octave
+  int64_t input_px = 0;
+  int64_t bands = 0;
+};
+
+void plan_add(Plan* pl, const DevParams& p, int height, int width, int64_t times) {
+  if (pl->tiles.empty()) {
+    pl->tiles.assign((size_t)kNumTileH * p.n_oct, 0);
+    pl->pixels.assign(p.n_oct, 0);
+  }
+  for (int k = 0; k < p.n_oct; ++k) {
+    int hk, wk;
+    octave_dims(height, width, p.upsample, k, &hk, &wk);
+    for (int c = 0; c < kNumTileH; ++c)
+      pl->tiles[k * kNumTileH + c] += times * cdiv(wk, kTileW) * cdiv(hk, tile_h_of(c));
+    pl->pixels[k] += times * (int64_t)hk * wk;
+  }
+  pl->input_px += times * (int64_t)height * width;
+  pl->bands += times * region_tail(height, width, layout_cfg(p)).total_bands;
+}
+
+HdrPtrs header_ptrs(char* ws, int n) {
   Header hd;
   make_header(n, &hd);
   HdrPtrs hp;
@@ -481,48 +498,59 @@ sift_status launch_batch(const sift_handle* h, const Config& cfg, int32_t n,
   hp.band_prefix = reinterpret_cast<int*>(ws + hd.band_prefix);
   hp.cand_prefix = reinterpret_cast<int*>(ws + hd.cand_prefix);
   hp.kp_prefix = reinterpret_cast<int*>(ws + hd.kp_prefix);
+  return hp;
+}
 
-  // image table, a chunk of entries per launch
-  int prec = prof_begin(kStSetup, 0.0, stream);
-  std::vector<int64_t> tiles(kNumTileH * p.n_oct, 0);   // [octave][class]
-  std::vector<int64_t> pixels(p.n_oct, 0);
-  int64_t input_px = 0;
-  int64_t bands = 0;
-  int64_t off = hd.bytes;
+// The image table: entries[i] copied into the workspace, a chunk of entries
+// per setup launch (kernel arguments carry them; nothing is copied from host
+// memory by the runtime).
+sift_status write_table(const std::vector<ImgEntry>& entries, const HdrPtrs& hp,
+                        hipStream_t stream) {
   SetupChunk chunk;
   std::memset(&chunk, 0, sizeof chunk);
+  const int n = (int)entries.size();
   for (int i = 0; i < n; ++i) {
-    ImgEntry& e = chunk.e[chunk.count];
-    e.src = d_images[i];
-    e.src_pitch = pitches[i];
-    e.h = heights[i];
-    e.w = widths[i];
-    e.region = off;
-    e.kp = outs[i].keypoints;
-    e.desc = outs[i].descriptors;
-    e.count = outs[i].count;
-    e.n_found = outs[i].n_found;
-    e.n_cand = outs[i].n_candidates;
-    e.cap = outs[i].capacity;
-    e.pad = 0;
-    off += region_bytes(h, heights[i], widths[i]);
-    for (int k = 0; k < p.n_oct; ++k) {
-      int hk, wk;
-      octave_dims(heights[i], widths[i], p.upsample, k, &hk, &wk);
-      for (int c = 0; c < kNumTileH; ++c) tiles[k * kNumTileH + c] += cdiv(wk, kTileW) * cdiv(hk, tile_h_of(c));
-      pixels[k] += (int64_t)hk * wk;
-    }
-    input_px += (int64_t)heights[i] * widths[i];
-    bands += region_tail(heights[i], widths[i], lc).total_bands;
+    chunk.e[chunk.count] = entries[i];
     if (++chunk.count == kSetupChunk || i == n - 1) {
-      if ((st = check_hip(launch_setup(hp, chunk, stream), "setup")) != SIFT_OK) return st;
+      sift_status st = check_hip(launch_setup(hp, chunk, stream), "setup");
+      if (st != SIFT_OK) return st;
       chunk.first = i + 1;
       chunk.count = 0;
     }
   }
-  for (int64_t t : tiles)
+  return SIFT_OK;
+}
+
+ImgEntry make_entry(const float* img, int64_t pitch, int height, int width, int64_t region,
+                    const sift_output& o) {
+  ImgEntry e;
+  std::memset(&e, 0, sizeof e);
+  e.src = img;
+  e.src_pitch = pitch;
+  e.h = height;
+  e.w = width;
+  e.region = region;
+  e.kp = o.keypoints;
+  e.desc = o.descriptors;
+  e.count = o.count;
+  e.n_found = o.n_found;
+  e.n_cand = o.n_candidates;
+  e.cap = o.capacity;
+  return e;
+}
+
+// Every stage after the table is in place: prefix tables, pyramid, detection,
+// compaction, refinement, orientation, descriptors.  Grids come from `plan`;
+// each kernel reads the actual work counts from the table on the device and
+// lets surplus work-groups go, so a plan may over-cover the images.
+sift_status launch_stages(const sift_handle* h, const Config& cfg, int32_t n, const Plan& plan,
+                          char* ws, const HdrPtrs& hp, hipStream_t stream) {
+  sift_status st = SIFT_OK;
+  const DevParams& p = cfg.dev;
+  for (int64_t t : plan.tiles)
     if (t > INT32_MAX - kXcds) return fail(SIFT_ERR_TOO_LARGE, "batch has too many tiles");
-  if (bands > INT32_MAX) return fail(SIFT_ERR_TOO_LARGE, "batch has too many bands");
+  if (plan.bands > INT32_MAX) return fail(SIFT_ERR_TOO_LARGE, "batch has too many bands");
+  int prec = prof_begin(kStSetup, 0.0, stream);
   if ((st = check_hip(launch_finalize(hp, n, p, stream), "finalize")) != SIFT_OK) return st;
   prof_end(prec, stream);
 
@@ -532,7 +560,7 @@ sift_status launch_batch(const sift_handle* h, const Config& cfg, int32_t n,
       BlurArgs a;
       std::memset(&a, 0, sizeof a);
       const Taps& t = lv == 0 ? cfg.init : cfg.inc[lv - 1];
-      const int cls = blur_class(h->params.tile_rows, &tiles[k * kNumTileH]);
+      const int cls = blur_class(h->params.tile_rows, &plan.tiles[k * kNumTileH]);
       const int th = tile_h_of(cls);
       a.ws = ws;
       a.table = hp.table;
@@ -548,28 +576,32 @@ sift_status launch_batch(const sift_handle* h, const Config& cfg, int32_t n,
       std::memcpy(a.taps, t.g, sizeof(float) * (2 * t.radius + 1));
       // algorithmic bytes: the source read once (input pixels for the first
       // level), the level written once, plus level 0 written when subsampling
-      double bytes = 8.0 * pixels[k];
-      if (lv == 0 && p.upsample) bytes = 4.0 * pixels[k] + 4.0 * input_px;
-      if (a.mode == kSrcDown) bytes += 4.0 * pixels[k];
+      double bytes = 8.0 * plan.pixels[k];
+      if (lv == 0 && p.upsample) bytes = 4.0 * plan.pixels[k] + 4.0 * plan.input_px;
+      if (a.mode == kSrcDown) bytes += 4.0 * plan.pixels[k];
       char label[32];
       std::snprintf(label, sizeof label, "o%d l%d R%d", k + p.o0, lv, t.radius);
       // a vertical and a horizontal pass of 2R + 1 taps per output pixel
-      prec = prof_begin(kStBlur, bytes, stream, label, 2.0 * (2 * t.radius + 1) * pixels[k]);
-      const int grid = (int)((tiles[k * kNumTileH + cls] + kXcds - 1) / kXcds * kXcds);
-      if ((st = check_hip(launch_blur(a, t.radius, grid, stream), "blur")) != SIFT_OK) return st;
+      prec = prof_begin(kStBlur, bytes, stream, label, 2.0 * (2 * t.radius + 1) * plan.pixels[k]);
+      const int grid = (int)((plan.tiles[k * kNumTileH + cls] + kXcds - 1) / kXcds * kXcds);
+      if (grid > 0 && (st = check_hip(launch_blur(a, t.radius, grid, stream), "blur")) != SIFT_OK)
+        return st;
       prof_end(prec, stream);
     }
   }
   // detection and ordered compaction
   int64_t all_px = 0;
-  for (int k = 0; k < p.n_oct; ++k) all_px += pixels[k];
+  for (int k = 0; k < p.n_oct; ++k) all_px += plan.pixels[k];
+  const int bands = (int)plan.bands;
   // detection reads the s+3 levels once and writes one mask bit per pixel-layer
   prec = prof_begin(kStDetect, (4.0 * (p.s + 3) + p.s / 8.0) * all_px, stream);
-  if ((st = check_hip(launch_detect(ws, hp, n, p, (int)bands, stream), "detect")) != SIFT_OK) return st;
+  if (bands > 0 && (st = check_hip(launch_detect(ws, hp, n, p, bands, stream), "detect")) != SIFT_OK)
+    return st;
   prof_end(prec, stream);
   prec = prof_begin(kStCompact, (p.s / 4.0) * all_px, stream);
   if ((st = check_hip(launch_band_scan(ws, hp, n, p, stream), "band scan")) != SIFT_OK) return st;
-  if ((st = check_hip(launch_emit(ws, hp, n, p, (int)bands, stream), "emit")) != SIFT_OK) return st;
+  if (bands > 0 && (st = check_hip(launch_emit(ws, hp, n, p, bands, stream), "emit")) != SIFT_OK)
+    return st;
   if ((st = check_hip(launch_img_prefix(ws, hp, n, p, 0, stream), "prefix")) != SIFT_OK) return st;
   prof_end(prec, stream);
   // per-candidate stages; grids are persistent, work counts are read on the device
@@ -591,6 +623,31 @@ sift_status launch_batch(const sift_handle* h, const Config& cfg, int32_t n,
   return SIFT_OK;
 }
 
+// The launch sequence of one (sub-)batch on `stream`; arguments already checked.
+sift_status launch_batch(const sift_handle* h, const Config& cfg, int32_t n,
+                         const float* const* d_images, const int32_t* heights,
+                         const int32_t* widths, const int64_t* pitches, void* d_workspace,
+                         const sift_output* outs, hipStream_t stream) {
+  char* ws = static_cast<char*>(d_workspace);
+  const DevParams& p = cfg.dev;
+  const LayoutCfg lc = layout_cfg(p);
+  Header hd;
+  make_header(n, &hd);
+  const HdrPtrs hp = header_ptrs(ws, n);
+  std::vector<ImgEntry> entries;
+  Plan plan;
+  int64_t off = hd.bytes;
+  for (int i = 0; i < n; ++i) {
+    entries.push_back(make_entry(d_images[i], pitches[i], heights[i], widths[i], off, outs[i]));
+    off += region_tail(heights[i], widths[i], lc).bytes;
+    plan_add(&plan, p, heights[i], widths[i], 1);
+  }
+  const int prec = prof_begin(kStSetup, 0.0, stream);
+  sift_status st = write_table(entries, hp, stream);
+  prof_end(prec, stream);
+  if (st != SIFT_OK) return st;
+  return launch_stages(h, cfg, n, plan, ws, hp, stream);
+}
 
 }  // namespace
 
@@ -690,6 +747,173 @@ sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_
   return check_hip(e, "sub-batch streams");
 }
 
+
+// ---------------------------------------------------------------------------
+// Buckets: one launch sequence recorded as a graph for up to n_slots images of
+// at most max_height x max_width each.  The graph's grids cover every slot at
+// the largest size; the image table it reads is rewritten by setup launches
+// before every replay, and each kernel reads the actual sizes from it.
+
+}  // extern "C"
+
+struct sift_bucket {
+  sift_handle* h = nullptr;
+  int cfg = 0;
+  int n_slots = 0, max_h = 0, max_w = 0;
+  char* ws = nullptr;
+  int64_t slot_bytes = 0;   // one image region at the largest size
+  int64_t sink = 0;         // scratch outputs of empty slots
+  int64_t slots = 0;        // first slot region
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr int64_t kSinkBytes = 1024;
+
+sift_status bucket_layout(const sift_handle* h, int32_t n_slots, int32_t max_h, int32_t max_w,
+                          int64_t* slot_bytes, int64_t* sink, int64_t* slots, int64_t* total) {
+  if (!h) return fail(SIFT_ERR_INVALID_ARG, "null handle");
+  if (n_slots < 1 || n_slots > kMaxBatch)
+    return fail(SIFT_ERR_INVALID_ARG, "n_slots must be in 1..%d", kMaxBatch);
+  sift_status st = validate_size(h, max_h, max_w);
+  if (st != SIFT_OK) return st;
+  Header hd;
+  make_header(n_slots, &hd);
+  *sink = hd.bytes;
+  *slots = hd.bytes + kSinkBytes;
+  *slot_bytes = region_bytes(h, max_h, max_w);
+  *total = *slots + (int64_t)n_slots * *slot_bytes;
+  return SIFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sift_status sift_bucket_workspace_size(const sift_handle* h, int32_t n_slots, int32_t max_height,
+                                       int32_t max_width, size_t* bytes) {
+  if (!bytes) return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  int64_t sb, sink, slots, total;
+  sift_status st = bucket_layout(h, n_slots, max_height, max_width, &sb, &sink, &slots, &total);
+  if (st != SIFT_OK) return st;
+  *bytes = (size_t)total;
+  return SIFT_OK;
+}
+
+sift_status sift_bucket_create(sift_handle* h, int32_t n_slots, int32_t max_height,
+                               int32_t max_width, void* d_workspace, size_t workspace_bytes,
+                               sift_bucket** out) {
+  if (!out || !d_workspace) return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  int64_t sb, sink, slots, total;
+  sift_status st = bucket_layout(h, n_slots, max_height, max_width, &sb, &sink, &slots, &total);
+  if (st != SIFT_OK) return st;
+  if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0)
+    return fail(SIFT_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if ((int64_t)workspace_bytes < total)
+    return fail(SIFT_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes, need %lld", workspace_bytes,
+                (long long)total);
+  const int cfg = cfg_index(h, max_height, max_width);
+  const Config& c = h->cfg[cfg];
+  Plan plan;
+  plan_add(&plan, c.dev, max_height, max_width, n_slots);
+  char* ws = static_cast<char*>(d_workspace);
+  const HdrPtrs hp = header_ptrs(ws, n_slots);
+  hipStream_t cap = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return check_hip(e, "capture stream");
+  e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    hipStreamDestroy(cap);
+    return check_hip(e, "begin capture");
+  }
+  sift::set_capturing(true);
+  st = launch_stages(h, c, n_slots, plan, ws, hp, cap);
+  sift::set_capturing(false);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cap, &graph);
+  hipStreamDestroy(cap);
+  if (st != SIFT_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return check_hip(e, "end capture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    hipGraphDestroy(graph);
+    return check_hip(e, "instantiate");
+  }
+  sift_bucket* b = new sift_bucket();
+  b->h = h;
+  b->cfg = cfg;
+  b->n_slots = n_slots;
+  b->max_h = max_height;
+  b->max_w = max_width;
+  b->ws = ws;
+  b->slot_bytes = sb;
+  b->sink = sink;
+  b->slots = slots;
+  b->graph = graph;
+  b->exec = exec;
+  *out = b;
+  return SIFT_OK;
+}
+
+sift_status sift_bucket_launch(sift_bucket* b, int32_t n, const float* const* d_images,
+                               const int32_t* heights, const int32_t* widths,
+                               const int64_t* pitches, const sift_output* outs, void* stream_v) {
+  if (!b || !d_images || !heights || !widths || !pitches || !outs)
+    return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  if (n < 1 || n > b->n_slots)
+    return fail(SIFT_ERR_INVALID_ARG, "%d images for a bucket of %d slots", n, b->n_slots);
+  for (int i = 0; i < n; ++i) {
+    if (!d_images[i]) return fail(SIFT_ERR_INVALID_ARG, "image %d is null", i);
+    if (heights[i] > b->max_h || widths[i] > b->max_w)
+      return fail(SIFT_ERR_INVALID_ARG, "image %d (%dx%d) exceeds the bucket's %dx%d", i,
+                  heights[i], widths[i], b->max_h, b->max_w);
+    sift_status st = validate_size(b->h, heights[i], widths[i]);
+    if (st != SIFT_OK) return st;
+    if (cfg_index(b->h, heights[i], widths[i]) != b->cfg)
+      return fail(SIFT_ERR_INVALID_ARG,
+                  "image %d takes the other octave structure (upsample_max_pixels)", i);
+    if (pitches[i] < widths[i]) return fail(SIFT_ERR_INVALID_ARG, "image %d: pitch < width", i);
+    if (!outs[i].keypoints || !outs[i].descriptors || !outs[i].count)
+      return fail(SIFT_ERR_INVALID_ARG, "image %d: null output pointer", i);
+    if (outs[i].capacity < 0) return fail(SIFT_ERR_INVALID_ARG, "image %d: negative capacity", i);
+  }
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_v);
+  // empty slots: a 0 x 0 image (no work items) whose outputs land in the sink
+  sift_output sink;
+  std::memset(&sink, 0, sizeof sink);
+  sink.keypoints = reinterpret_cast<sift_keypoint*>(b->ws + b->sink);
+  sink.descriptors = reinterpret_cast<float*>(b->ws + b->sink + 64);
+  sink.count = reinterpret_cast<int32_t*>(b->ws + b->sink + kSinkBytes - 16);
+  sink.capacity = 0;
+  std::vector<ImgEntry> entries;
+  for (int i = 0; i < b->n_slots; ++i) {
+    const int64_t region = b->slots + (int64_t)i * b->slot_bytes;
+    if (i < n)
+      entries.push_back(make_entry(d_images[i], pitches[i], heights[i], widths[i], region, outs[i]));
+    else
+      entries.push_back(make_entry(reinterpret_cast<const float*>(b->ws + b->sink), 0, 0, 0,
+                                   region, sink));
+  }
+  sift_status st = write_table(entries, header_ptrs(b->ws, b->n_slots), stream);
+  if (st != SIFT_OK) return st;
+  return check_hip(hipGraphLaunch(b->exec, stream), "bucket launch");
+}
+
+sift_status sift_bucket_destroy(sift_bucket* b) {
+  if (!b) return SIFT_OK;
+  hipError_t e = hipGraphExecDestroy(b->exec);
+  const hipError_t e2 = hipGraphDestroy(b->graph);
+  delete b;
+  if (e == hipSuccess) e = e2;
+  return check_hip(e, "bucket destroy");
+}
 
 sift_status sift_extract(sift_handle* h, const float* d_image, int32_t height, int32_t width,
                          int64_t pitch, void* d_workspace, size_t workspace_bytes,

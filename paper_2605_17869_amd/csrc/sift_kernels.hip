@@ -107,6 +107,7 @@ __global__ __launch_bounds__(kDetectWaves * 64) void k_detect(char* ws, HdrPtrs 
   __shared__ int s_cnt[kDetectWaves][S];
   const int* bp = hp.band_prefix;
   const int item = blockIdx.x;
+  if (item >= bp[n]) return;   // a grid sized for larger images than the table's
   const int img = find_owner(bp, n, item);
   const int lb = item - bp[img];
   const ImgEntry e = hp.table[img];
@@ -205,6 +206,7 @@ __global__ __launch_bounds__(256) void k_band_scan(char* ws, HdrPtrs hp, int n, 
 __global__ __launch_bounds__(64) void k_emit(char* ws, HdrPtrs hp, int n, DevParams p) {
   const int* bp = hp.band_prefix;
   const int item = blockIdx.x;
+  if (item >= bp[n]) return;
   const int img = find_owner(bp, n, item);
   const int lb = item - bp[img];
   const ImgEntry e = hp.table[img];

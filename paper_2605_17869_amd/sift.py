@@ -171,6 +171,18 @@ _SIGNATURES = {
     "sift_match_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(SiftMatchPair),
                                         ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t,
                                         ctypes.c_void_p]),
+    "sift_bucket_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "sift_bucket_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "sift_bucket_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_void_p),
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int64),
+                                          ctypes.POINTER(SiftOutput), ctypes.c_void_p]),
+    "sift_bucket_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sift_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sift_last_error": (ctypes.c_char_p, []),
 }
@@ -409,6 +421,20 @@ class Extractor:
                "sift_graph_create")
         return BatchGraph(self.lib, g, list(images), feats, ws)
 
+    def bucket(self, n_slots: int, max_height: int, max_width: int):
+        """A replayable launch sequence for up to n_slots images of at most
+        max_height x max_width (``sift_bucket_*``); owns its workspace."""
+        import torch
+        need = ctypes.c_size_t()
+        _check(self.lib.sift_bucket_workspace_size(self.handle, n_slots, max_height, max_width,
+                                                   ctypes.byref(need)), "sift_bucket_workspace_size")
+        ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+        hb = ctypes.c_void_p()
+        _check(self.lib.sift_bucket_create(self.handle, n_slots, max_height, max_width,
+                                           ctypes.c_void_p(ws.data_ptr()), need.value,
+                                           ctypes.byref(hb)), "sift_bucket_create")
+        return Bucket(self, hb, ws, n_slots)
+
     def autotune(self, images, warmup: int = 1, reps: int = 3, outs=None, workspace=None,
                  stream=None):
         """(best tile_rows, {tile_rows: ms}) for this batch; see sift_autotune_batch."""
@@ -436,6 +462,43 @@ class Extractor:
         flat = workspace[off:off + 4 * n].view(torch.float32)
         arr = flat.view(lh.value, lp.value)[:, :lw.value].cpu().numpy().astype(np.float64)
         return arr + 0.5
+
+
+class Bucket:
+    """A size bucket (``sift_bucket_*``): replays its recorded launch sequence
+    for any images that fit; keeps its extractor and workspace alive."""
+
+    def __init__(self, extractor, handle, workspace, n_slots):
+        self.ex, self.handle, self._ws, self.n_slots = extractor, handle, workspace, n_slots
+
+    def launch(self, images, outs=None, capacity: int | None = None, stream=None) -> list:
+        import torch
+        n = len(images)
+        for im in images:
+            if im.dim() != 2 or im.dtype != torch.float32 or not im.is_cuda or im.stride(1) != 1:
+                raise ValueError("images must be 2-D CUDA tensors with contiguous rows")
+        feats = outs if outs is not None else [self.ex.alloc_features(capacity) for _ in range(n)]
+        ptrs = (ctypes.c_void_p * n)(*[im.data_ptr() for im in images])
+        hs = (ctypes.c_int32 * n)(*[im.shape[0] for im in images])
+        wss = (ctypes.c_int32 * n)(*[im.shape[1] for im in images])
+        pitches = (ctypes.c_int64 * n)(*[im.stride(0) for im in images])
+        o = (SiftOutput * n)(*[self.ex._output(f, f.keypoints.shape[0] if capacity is None
+                                               else int(capacity)) for f in feats])
+        _check(self.ex.lib.sift_bucket_launch(self.handle, n, ptrs, hs, wss, pitches, o,
+                                              _stream_handle(stream)), "sift_bucket_launch")
+        return feats
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            st = self.ex.lib.sift_bucket_destroy(self.handle)
+            self.handle = None
+            _check(st, "sift_bucket_destroy")
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BatchGraph:

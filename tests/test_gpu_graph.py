@@ -54,3 +54,55 @@ def test_autotune_picks_a_candidate():
     assert best in (64, 128, 256, 512)
     assert all(v > 0 for v in ms.values())
     assert ms[best] == min(ms.values())
+
+
+def test_bucket_replays_images_of_other_sizes():
+    """One bucket (4 slots, at most 220 x 320) serves launches of 3, then 4,
+    then 1 images of sizes it was not recorded with; every result equals
+    sift_extract on the image alone, bit for bit, with eager work between
+    replays."""
+    torch = require_gpu()
+    from paper_2605_17869_amd import Extractor
+    from paper_2605_17869_amd.sift import SiftError
+    ex = Extractor(SETTINGS)
+    bk = ex.bucket(4, 220, 320)
+    rounds = [[(120, 160), (200, 150), (96, 300)],
+              [(220, 320), (64, 64), (150, 200), (100, 250)],
+              [(77, 91)]]
+    for rnd, sizes in enumerate(rounds):
+        imgs = [synth.blob_image(900 + 10 * rnd + k, h, w, max(1, int(h * w * 3 * synth.BLOB_DENSITY)))
+                for k, (h, w) in enumerate(sizes)]
+        ref = [extract(ex, im) for im in imgs]
+        bufs = [torch.from_numpy(im).cuda() for im in imgs]
+        feats = bk.launch(bufs)
+        torch.cuda.synchronize()
+        for k, f in enumerate(feats):
+            kp, desc, nf, nc = f.host()
+            assert digest(kp, desc) == digest(ref[k][0], ref[k][1]), (rnd, k)
+            assert (nf, nc) == ref[k][2:], (rnd, k)
+        say(f"bucket round {rnd}: {len(sizes)} images match sift_extract")
+    big = torch.zeros((221, 100), dtype=torch.float32, device="cuda")
+    with pytest.raises(SiftError):
+        bk.launch([big])
+    five = [torch.full((100, 100), 0.5, dtype=torch.float32, device="cuda")] * 5
+    with pytest.raises(SiftError):
+        bk.launch(five)
+    bk.close()
+
+
+def test_bucket_needs_one_octave_structure():
+    torch = require_gpu()
+    from paper_2605_17869_amd import Extractor
+    from paper_2605_17869_amd.sift import SiftError
+    ex = Extractor(dict(SETTINGS, upsample_max_pixels=20000))
+    bk = ex.bucket(2, 200, 200)            # 40000 px: built without octave -1
+    small = torch.full((100, 150), 0.5, dtype=torch.float32, device="cuda")   # 15000 px: upsampled
+    with pytest.raises(SiftError):
+        bk.launch([small])
+    img = synth.blob_image(950, 180, 190, 60)
+    ref = extract(ex, img)
+    f, = bk.launch([torch.from_numpy(img).cuda()])
+    torch.cuda.synchronize()
+    kp, desc, nf, nc = f.host()
+    assert digest(kp, desc) == digest(ref[0], ref[1])
+    bk.close()
