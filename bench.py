@@ -239,6 +239,43 @@ def serve_points(unique_images: int, requests: int, warmup_requests: int, fracti
                     largest_batch=stats["largest_batch"],
                     overlapped_batches=stats["overlapped_batches"])
 
+    # one batch of the random-size images: launch sequence against size
+    # buckets recorded for the largest possible size and for the batch's own
+    # largest image (the same bits either way)
+    def bucket_cmp():
+        batch = d_imgs[:64]
+        bo = [ex.alloc_features(cap) for _ in batch]
+        wsb = torch.empty(ex.batch_workspace_size([tuple(b.shape) for b in batch]),
+                          dtype=torch.uint8, device=dev)
+
+        def tm(fn, reps=10):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            return round(a.elapsed_time(b) / reps, 4)
+
+        res = {"images": len(batch),
+               "launch_sequence_ms": tm(lambda: ex.extract_batch(batch, outs=bo, workspace=wsb))}
+        ref = [digest(*f.host()[:2]) for f in bo]
+        for name, (mh, mw) in (("bucket_2048x2048_ms", (2048, 2048)),
+                               ("bucket_batch_max_ms", (max(b.shape[0] for b in batch),
+                                                        max(b.shape[1] for b in batch)))):
+            bk = ex.bucket(len(batch), mh, mw)
+            res[name] = tm(lambda: bk.launch(batch, outs=bo))
+            res[name.replace("_ms", "_identical")] = ref == [digest(*f.host()[:2]) for f in bo]
+            bk.close()
+        del wsb, bo
+        return res
+
+    buckets = bucket_cmp()
+    print(f"[serve] buckets {buckets}", file=sys.stderr, flush=True)
+
     run(None, 64, 2)   # warm-up
     sat = run(None, 64, 2)
     sat_rate = sat["images_per_s"]
@@ -255,14 +292,14 @@ def serve_points(unique_images: int, requests: int, warmup_requests: int, fracti
         points.append(dict(qps=round(qps, 1), fraction=f, batched=batched, one_at_a_time=plain))
         print(f"[serve] qps {qps:.1f}: batched {batched} one-at-a-time {plain}", file=sys.stderr,
               flush=True)
-    return wl, imgs, sat, one, points
+    return wl, imgs, sat, one, points, buckets
 
 
 def serve_bench(args):
     """Full serving sweep as its own JSON line (``--serve``)."""
     fr = [float(x) for x in args.qps_fractions.split(",")]
-    wl, imgs, sat, one, points = serve_points(args.unique_images, args.requests,
-                                              args.warmup_requests, fr, True)
+    wl, imgs, sat, one, points, buckets = serve_points(args.unique_images, args.requests,
+                                                       args.warmup_requests, fr, True)
     sat_rate = sat["images_per_s"]
     arena = 24 << 30
     mpix = float(np.mean([h * w for h, w in wl.sizes])) / 1e6
@@ -275,6 +312,7 @@ def serve_bench(args):
                    "unique_images": len(imgs), "mean_mpix": round(mpix, 3),
                    "max_batch": 64, "max_inflight": 2, "arena_gib": arena >> 30},
         "saturation": sat, "one_at_a_time_saturation": one, "points": points,
+        "buckets": buckets,
     }
     print(json.dumps(line), flush=True)
 
@@ -346,16 +384,18 @@ def main():
     sizes = [tuple(im.shape) for im in imgs]
     stream = torch.cuda.current_stream()
     tune = None
-    tile_rows = args.tile_rows
+    tile_rows, n_streams = args.tile_rows, args.n_streams
     if tile_rows == 0 and not args.no_autotune:
+        # both launch knobs (chunk-height cap x sub-batch count), timed afresh
+        # in the form the line reports (graph replay, unless --no-graph)
         probe = sm.Extractor(wl.settings)
-        ws0 = torch.empty(probe.batch_workspace_size(sizes), dtype=torch.uint8, device=dev)
-        tile_rows, tune_ms = probe.autotune(d_imgs, warmup=1, reps=3, workspace=ws0,
-                                            stream=stream)
-        tune = {str(k): round(v, 4) for k, v in tune_ms.items()}
-        del probe, ws0
-        print(f"[bench] autotune: tile_rows {tile_rows} ({tune})", file=sys.stderr, flush=True)
-    settings = dict(wl.settings, tile_rows=tile_rows, n_streams=args.n_streams)
+        tune = probe.tune(d_imgs, warmup=1, reps=5, as_graph=not args.no_graph, stream=stream)
+        tile_rows = tune["tile_rows"]
+        if n_streams == 0:
+            n_streams = tune["n_streams"]
+        del probe
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
+    settings = dict(wl.settings, tile_rows=tile_rows, n_streams=n_streams)
     ex = sm.Extractor(settings)
     ws = torch.empty(ex.batch_workspace_size(sizes), dtype=torch.uint8, device=dev)
     outs = [ex.alloc_features() for _ in range(n)]
@@ -397,6 +437,21 @@ def main():
               file=sys.stderr, flush=True)
         if graph_identical and ms_graph < ms:
             ms, mode = ms_graph, "graph replay"
+
+    # the same batch through a size bucket recorded for its largest image
+    ms_bucket, bucket_identical = None, None
+    if not args.no_graph:
+        maxh, maxw = max(h for h, _ in sizes), max(w for _, w in sizes)
+        outs_b = [ex.alloc_features() for _ in range(n)]
+        bk = ex.bucket(n, maxh, maxw)
+        ms_bucket, _ = timed(lambda: bk.launch(d_imgs, outs=outs_b, stream=stream), args.warmup,
+                             args.steps)
+        bucket_identical = all(digest(a[0], a[1]) == digest(b[0], b[1]) and a[2:] == b[2:]
+                               for a, b in zip(batch_host, [f.host() for f in outs_b]))
+        bk.close()
+        del outs_b
+        print(f"[bench] bucket replay: {ms_bucket:.3f} ms/step, identical={bucket_identical}",
+              file=sys.stderr, flush=True)
 
     # plain per-image path on the same images
     ms1, identical = None, None
@@ -496,13 +551,14 @@ def main():
     if not args.no_serve_point:
         del ws
         torch.cuda.empty_cache()
-        swl, simgs, sat, _, pts = serve_points(64, 2000, 200, [0.5], False)
+        swl, simgs, sat, _, pts, buckets = serve_points(64, 2000, 200, [0.5], False)
         serving = {"workload": swl.name, "unique_images": len(simgs), "requests": 2000,
                    "warmup_requests": 200, "max_batch": 64, "max_inflight": 2,
                    "saturation_images_per_s": sat["images_per_s"],
                    "at_half_saturation": pts[0]["batched"], "qps": pts[0]["qps"],
                    "latency": "entry into submit (or the scheduled arrival, if later) to "
-                              "observed completion"}
+                              "observed completion",
+                   "one_batch_of_64_launch_vs_buckets": buckets}
 
     matching = None
     if not args.no_match:
@@ -525,7 +581,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "images": n, "image_size": (f"{sizes[0][1]}x{sizes[0][0]}" if len(set(sizes)) == 1
                                   else f"mixed, mean {mpix / n:.3f} Mpix"),
-                   "tile_rows": tile_rows, "upsample": wl.settings["upsample"], "octaves": wl.settings["n_octaves"] +
+                   "tile_rows": tile_rows, "n_streams": n_streams,
+                   "upsample": wl.settings["upsample"], "octaves": wl.settings["n_octaves"] +
                    wl.settings["upsample"], "parallelism": "none (one GPU)"},
         "mpix_per_s": round(mpix / (ms * 1e-3), 2),
         "per_image_path": ({"images_per_s": round(n / (ms1 * 1e-3), 2),
@@ -535,7 +592,9 @@ def main():
         "ms_per_step_launch_sequence": round(ms_eager, 4),
         "ms_per_step_graph_replay": round(ms_graph, 4) if ms_graph else None,
         "bitwise_identical_graph_vs_launch_sequence": graph_identical,
-        "autotune_ms_per_tile_rows": tune,
+        "ms_per_step_bucket_replay": round(ms_bucket, 4) if ms_bucket else None,
+        "bitwise_identical_bucket_vs_launch_sequence": bucket_identical,
+        "autotune": tune,
         "bitwise_identical_batched_vs_per_image": identical,
         "keypoints_per_image": round(n_kp / n, 1),
         "stages": stages,

@@ -318,6 +318,41 @@ sift_status sift_autotune_batch(const sift_params* p, int32_t n, const float* co
                                 float* ms);
 
 /*
+ * Tuning over both launch knobs, with a persisted cache.  sift_autotune
+ * times sift_extract_batch on the given batch for every blur chunk-height cap
+ * (64, 128, 256, 512) and every sub-batch count (1, 2, 4, 8, at most n) --
+ * all of them give bit-identical results -- and returns the fastest pair in
+ * *out.  With cache_path non-NULL it first looks the batch up in that text
+ * file (one line per entry: key, tile_rows, n_streams, ms; the last entry of
+ * a key wins) and, on a hit, returns the entry without timing (from_cache =
+ * 1); after timing it appends the winner.  The key names the device (name,
+ * architecture, compute units), the settings other than the two tuned fields,
+ * the image count, the total input pixels to two significant figures and the
+ * execution form: as_graph = 0 times the launch sequence (sift_extract_batch),
+ * 1 times replays of it recorded as a graph (sift_graph_*), whose best split
+ * can differ.  It synchronises on `stream` when it times; not for a capture
+ * or a hot loop.
+ */
+typedef struct {
+  int32_t tile_rows;    /* chosen chunk-height cap */
+  int32_t n_streams;    /* chosen sub-batch count */
+  float ms;             /* its mean time per batch, ms */
+  int32_t from_cache;   /* 1: read from the cache file, nothing timed */
+  int32_t n_tried;      /* candidates timed */
+} sift_tuning;
+
+/* Workspace that every candidate of sift_autotune fits in (a split into more
+ * sub-batches needs a few headers more); candidates that do not fit the
+ * workspace given to sift_autotune are skipped. */
+sift_status sift_autotune_workspace_size(const sift_params* p, int32_t n, const int32_t* heights,
+                                         const int32_t* widths, size_t* bytes);
+sift_status sift_autotune(const sift_params* p, int32_t n, const float* const* d_images,
+                          const int32_t* heights, const int32_t* widths, const int64_t* pitches,
+                          void* d_workspace, size_t workspace_bytes, const sift_output* outs,
+                          void* stream, int32_t warmup, int32_t reps, int32_t as_graph,
+                          const char* cache_path, sift_tuning* out);
+
+/*
  * Serving (a request stream of images of any sizes).
  *
  * The paper extracts one image per call; this is a continuous-batching

@@ -86,6 +86,11 @@ MATCH_DTYPE = np.dtype([("query", "<i4"), ("train", "<i4"), ("similarity", "<f4"
                         ("distance", "<f4")])
 
 
+class SiftTuning(ctypes.Structure):
+    _fields_ = [("tile_rows", ctypes.c_int32), ("n_streams", ctypes.c_int32),
+                ("ms", ctypes.c_float), ("from_cache", ctypes.c_int32), ("n_tried", ctypes.c_int32)]
+
+
 # name -> (restype, argtypes)
 _SIGNATURES = {
     "sift_params_default": (ctypes.c_int, [ctypes.POINTER(SiftParams)]),
@@ -183,6 +188,18 @@ _SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_int64),
                                           ctypes.POINTER(SiftOutput), ctypes.c_void_p]),
     "sift_bucket_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sift_autotune": (ctypes.c_int, [ctypes.POINTER(SiftParams), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_void_p),
+                                     ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p,
+                                     ctypes.c_size_t, ctypes.POINTER(SiftOutput), ctypes.c_void_p,
+                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_char_p, ctypes.POINTER(SiftTuning)]),
+    "sift_autotune_workspace_size": (ctypes.c_int, [ctypes.POINTER(SiftParams), ctypes.c_int32,
+                                                    ctypes.POINTER(ctypes.c_int32),
+                                                    ctypes.POINTER(ctypes.c_int32),
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
     "sift_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sift_last_error": (ctypes.c_char_p, []),
 }
@@ -445,6 +462,31 @@ class Extractor:
                                             _stream_handle(stream), warmup, reps,
                                             ctypes.byref(best), ms), "sift_autotune_batch")
         return best.value, dict(zip((64, 128, 256, 512), list(ms)))
+
+    def tune(self, images, warmup: int = 1, reps: int = 3, cache_path: str | None = None,
+             as_graph: bool = False, outs=None, workspace=None, stream=None) -> dict:
+        """``sift_autotune``: the fastest (tile_rows, n_streams) for this batch
+        run as a launch sequence (or, ``as_graph``, as graph replays), from
+        ``cache_path`` when it holds the batch's key."""
+        import torch
+        if workspace is None:
+            n = len(images)
+            hs = (ctypes.c_int32 * n)(*[int(im.shape[0]) for im in images])
+            wss = (ctypes.c_int32 * n)(*[int(im.shape[1]) for im in images])
+            need = ctypes.c_size_t()
+            _check(self.lib.sift_autotune_workspace_size(ctypes.byref(self.params), n, hs, wss,
+                                                         ctypes.byref(need)),
+                   "sift_autotune_workspace_size")
+            workspace = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+        args, _, _ = self._batch_args(images, None, outs, workspace)
+        t = SiftTuning()
+        path = cache_path.encode() if cache_path else None
+        _check(self.lib.sift_autotune(ctypes.byref(self.params), *args, _stream_handle(stream),
+                                      warmup, reps, 1 if as_graph else 0, path, ctypes.byref(t)),
+               "sift_autotune")
+        return {"tile_rows": t.tile_rows, "n_streams": t.n_streams, "ms": round(t.ms, 4),
+                "from_cache": bool(t.from_cache), "candidates_timed": t.n_tried,
+                "timed_as": "graph replay" if as_graph else "launch sequence"}
 
     def level(self, workspace, height: int, width: int, octave: int, level: int):
         """Gaussian level (octave, level) of the last single-image extraction in

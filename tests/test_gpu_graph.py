@@ -106,3 +106,32 @@ def test_bucket_needs_one_octave_structure():
     kp, desc, nf, nc = f.host()
     assert digest(kp, desc) == digest(ref[0], ref[1])
     bk.close()
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    """sift_autotune times both knobs, appends the winner to the cache file,
+    and a second call with the same batch reads it back without timing; the
+    tuned handle gives the same bits as any other setting."""
+    torch = require_gpu()
+    from paper_2605_17869_amd import Extractor
+    ex = Extractor(SETTINGS)
+    imgs = images(6)
+    bufs = [torch.from_numpy(im).cuda() for im in imgs]
+    cache = str(tmp_path / "tune.txt")
+    first = ex.tune(bufs, warmup=1, reps=1, cache_path=cache)
+    say(f"tuned: {first}")
+    assert not first["from_cache"] and first["candidates_timed"] >= 4
+    assert first["tile_rows"] in (64, 128, 256, 512) and first["n_streams"] in (1, 2)
+    again = ex.tune(bufs, warmup=1, reps=1, cache_path=cache)
+    assert again["from_cache"] and again["candidates_timed"] == 0
+    assert (again["tile_rows"], again["n_streams"]) == (first["tile_rows"], first["n_streams"])
+    graph = ex.tune(bufs, warmup=1, reps=1, cache_path=cache, as_graph=True)
+    assert not graph["from_cache"] and graph["candidates_timed"] >= 4   # its own key
+    assert ex.tune(bufs, warmup=1, reps=1, cache_path=cache, as_graph=True)["from_cache"]
+    tuned = Extractor(dict(SETTINGS, tile_rows=first["tile_rows"], n_streams=first["n_streams"]))
+    ref = [extract(ex, im) for im in imgs]
+    feats = tuned.extract_batch(bufs)
+    torch.cuda.synchronize()
+    for k, f in enumerate(feats):
+        kp, desc, nf, nc = f.host()
+        assert digest(kp, desc) == digest(ref[k][0], ref[k][1])
