@@ -57,6 +57,7 @@ class Params:
     max_keypoints: int = 65536
     max_candidates: int = 65536   # detections refined, first ones in canonical order
     upsample_max_pixels: int = 0  # > 0: no octave -1 for images of more pixels than this
+    pyramid_fp16: int = 0         # 1: levels of every octave after the first stored as fp16
 
     @classmethod
     def from_settings(cls, settings: dict) -> "Params":
@@ -201,9 +202,21 @@ def check_size(height: int, width: int, p: Params):
         raise ValueError(f"image {height}x{width} too small for {p.n_octaves} octaves")
 
 
+def store_fp16(level: np.ndarray) -> np.ndarray:
+    """A level as held in fp16 storage (section 3.2, "GPU Pipeline Stages":
+    fp16 storage with fp32 compute, the first octave kept in fp32): the value
+    relative to mid-grey, L - 1/2, rounded to the nearest fp16 (ties to even),
+    read back as L.  Holding levels relative to mid-grey is this
+    implementation's storage convention; it changes no difference of levels."""
+    return (level - 0.5).astype(np.float16).astype(np.float64) + 0.5
+
+
 def scale_space(img: np.ndarray, p: Params) -> list:
     """Gaussian and DoG pyramid.  The next octave's level 0 is level s of the
-    current octave taken at every second pixel, with no further blur."""
+    current octave taken at every second pixel, with no further blur.  With
+    pyramid_fp16, every level of the octaves after the first is stored in fp16
+    (store_fp16) as soon as it is made, and the next level is blurred from the
+    stored value."""
     img = np.asarray(img, dtype=np.float32).astype(np.float64)
     p = effective_params(img.shape[0], img.shape[1], p)
     check_size(img.shape[0], img.shape[1], p)
@@ -213,9 +226,10 @@ def scale_space(img: np.ndarray, p: Params) -> list:
     o0 = -1 if p.upsample else 0
     octaves = []
     for o in range(o0, o0 + p.n_octaves + (1 if p.upsample else 0)):
-        levels = [level0]
+        store = store_fp16 if (p.pyramid_fp16 and o > o0) else (lambda x: x)
+        levels = [store(level0)]
         for sig in incs:
-            levels.append(gaussian_blur(levels[-1], sig))
+            levels.append(store(gaussian_blur(levels[-1], sig)))
         L = np.stack(levels)
         D = L[1:] - L[:-1]
         octaves.append(Octave(o, L, D))

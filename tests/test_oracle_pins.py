@@ -464,3 +464,58 @@ def test_upsample_limit_drops_octave_minus_one_above_the_size():
     assert np.array_equal(above.descriptors, off.descriptors)
     assert np.array_equal(at.keypoints, on.keypoints)
     assert min(above.keypoints["octave"]) == 0 and min(at.keypoints["octave"]) == -1
+
+
+# ---------------------------------------------------------------------------
+# fp16 pyramid storage (section 3.2, "GPU Pipeline Stages")
+
+def _fp16_pair(img, **kw):
+    from paper_2605_17869_amd import synth  # noqa: F401  (inputs only)
+    p32 = so.Params(n_octaves=3, **kw)
+    p16 = so.Params(n_octaves=3, pyramid_fp16=1, **kw)
+    return so.scale_space(img, p32), so.scale_space(img, p16)
+
+
+@pytest.mark.parametrize("up", [0, 1])
+def test_fp16_storage_keeps_the_first_octave_and_rounds_the_rest(up):
+    from paper_2605_17869_amd import synth
+    img = synth.blob_image(77, 90, 120, 40)
+    o32, o16 = _fp16_pair(img, upsample=up)
+    # the first octave is untouched, bit for bit
+    np.testing.assert_array_equal(o32[0].L, o16[0].L)
+    for a, b in zip(o32[1:], o16[1:]):
+        centred = b.L - 0.5
+        # every stored value is an fp16 number
+        np.testing.assert_array_equal(centred, centred.astype(np.float16).astype(np.float64))
+        # each of the s+3 levels adds at most half an fp16 ulp of |L - 1/2| <= 1/2
+        # (2^-12 for values in [1/4, 1/2)), and a unit-sum non-negative blur
+        # never grows an error: levels stay within (octave count x (s+3)) half-ulps
+        bound = (a.o - o32[0].o) * len(a.L) * 2.0 ** -12
+        assert np.max(np.abs(a.L - b.L)) <= bound
+        assert np.max(np.abs(a.L - b.L)) > 0.0
+
+
+def test_fp16_storage_of_a_constant_image_is_exact():
+    # blurring a constant leaves it constant up to the fp64 tap sum; stored in
+    # fp16 the later octaves hold exactly mid-grey
+    img = np.full((60, 80), 0.5, np.float32)
+    o32, o16 = _fp16_pair(img)
+    for a, b in zip(o32, o16):
+        assert np.max(np.abs(a.L - b.L)) < 1e-15
+    for b in o16[1:]:
+        assert np.all(b.L == 0.5)
+    assert len(so.sift(img, so.Params(n_octaves=3, pyramid_fp16=1)).keypoints) == 0
+
+
+def test_fp16_storage_leaves_first_octave_keypoints_unchanged():
+    from paper_2605_17869_amd import synth
+    img = synth.blob_image(78, 160, 200, 90)
+    r32 = so.sift(img, so.Params(n_octaves=3))
+    r16 = so.sift(img, so.Params(n_octaves=3, pyramid_fp16=1))
+
+    def first(r):
+        k = r.keypoints
+        sel = k["octave"] == 0
+        return k[sel].tobytes(), r.descriptors[sel].tobytes(), int(sel.sum())
+
+    assert first(r32) == first(r16) and first(r32)[2] > 5
