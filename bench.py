@@ -345,6 +345,7 @@ def main():
     ap.add_argument("--no-serve-point", action="store_true",
                     help="skip the serving point (saturation and p50/p99 at half of it)")
     ap.add_argument("--no-match", action="store_true", help="skip the matcher measurement")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the fp16-storage measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -452,6 +453,25 @@ def main():
         del outs_b
         print(f"[bench] bucket replay: {ms_bucket:.3f} ms/step, identical={bucket_identical}",
               file=sys.stderr, flush=True)
+
+    # the same batch with fp16 storage of the octaves after the first
+    fp16 = None
+    if not args.no_fp16:
+        ex16 = sm.Extractor(dict(settings, pyramid_fp16=1))
+        ws16 = torch.empty(ex16.batch_workspace_size(sizes), dtype=torch.uint8, device=dev)
+        outs16 = [ex16.alloc_features() for _ in range(n)]
+        ms16, _ = timed(lambda: ex16.extract_batch(d_imgs, outs=outs16, workspace=ws16,
+                                                   stream=stream), args.warmup, args.steps)
+        n16 = int(sum(int(f.counters[0].item()) for f in outs16))
+        fp16 = {"ms_per_step_launch_sequence": round(ms16, 4),
+                "images_per_s": round(n / (ms16 * 1e-3), 2),
+                "vs_fp32_launch_sequence": round(ms_eager / ms16, 3),
+                "workspace_bytes": int(ws16.numel()), "workspace_bytes_fp32": int(ws.numel()),
+                "keypoints_per_image": round(n16 / n, 1),
+                "note": "levels of the octaves after the first stored as fp16 (pyramid_fp16 = 1); "
+                        "parity against the oracle's fp16 mode under restated tolerances"}
+        del ex16, ws16, outs16
+        print(f"[bench] fp16 storage: {fp16}", file=sys.stderr, flush=True)
 
     # plain per-image path on the same images
     ms1, identical = None, None
@@ -604,6 +624,7 @@ def main():
                 "gbs": round(h2d_bytes / h2d_s / 1e9, 2),
                 "images_per_s_with_h2d": round(n / (ms * 1e-3 + h2d_s), 2),
                 "note": "pinned host buffers, one copy per image, before timing; not in value"},
+        "fp16_storage": fp16,
         "serving": serving,
         "matching": matching,
     }

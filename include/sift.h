@@ -102,6 +102,11 @@ typedef struct {
                                  paper's VRAM-adaptive suppression of the 2x base, which it
                                  applies above 4 MP (4000000) on a 4 GB GPU.  A batch may
                                  mix both kinds of image */
+  int32_t pyramid_fp16;       /* 0: every level fp32.  1: the levels of every octave after
+                                 the first are stored as fp16 (of L - 0.5, nearest even),
+                                 all arithmetic stays fp32 and the first octave stays fp32
+                                 (section 3.2, "GPU Pipeline Stages"): about half the pyramid
+                                 bytes of those octaves, at fp16 accuracy for their keypoints */
 } sift_params;
 
 /* One keypoint, 48 bytes.  Keypoints of an image come in canonical order:
@@ -213,6 +218,11 @@ sift_status sift_workspace_level(const sift_handle* h, int32_t height, int32_t w
                                  const void* d_workspace, int32_t octave, int32_t level,
                                  const float** d_level, int32_t* level_height,
                                  int32_t* level_width, int32_t* level_pitch);
+/* Bytes per stored element of the levels of that octave: 4 (fp32), or 2 (fp16,
+ * the octaves after the first with pyramid_fp16); *d_level then points at
+ * fp16 values. */
+sift_status sift_workspace_level_bytes(const sift_handle* h, int32_t height, int32_t width,
+                                       int32_t octave, int32_t* elem_bytes);
 
 /* Stage profiling (benchmarks and tests; not for production paths).
  * sift_profile_start begins recording, for every extraction this process then

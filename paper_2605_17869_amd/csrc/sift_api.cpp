@@ -144,6 +144,8 @@ sift_status validate_params(const sift_params& p) {
     return fail(SIFT_ERR_INVALID_ARG, "n_streams must be in 0..%d", kMaxParts);
   if (p.upsample_max_pixels < 0)
     return fail(SIFT_ERR_INVALID_ARG, "upsample_max_pixels must be >= 0");
+  if (p.pyramid_fp16 != 0 && p.pyramid_fp16 != 1)
+    return fail(SIFT_ERR_INVALID_ARG, "pyramid_fp16 must be 0 or 1");
   // Window sizes.  A refined keypoint has layer + offset below s + 1/2, so
   // its octave scale stays below sigma0 * 2^((s + 1/2) / s).  The descriptor
   // scans a square of half-side ceil(2.5 * cell * (|cos| + |sin|)) + 1 for
@@ -390,6 +392,7 @@ sift_status sift_create(const sift_params* p, sift_handle** out) {
     d.max_kp = p->max_keypoints;
     d.max_cand = p->max_candidates;
     d.n_dsp = p->n_dsp;
+    d.h16 = p->pyramid_fp16;
     d.sigma0 = p->sigma0;
     d.contrast_thr = p->contrast_threshold;
     d.pre_thr = p->prefilter_ratio * p->contrast_threshold;
@@ -573,12 +576,17 @@ sift_status launch_stages(const sift_handle* h, const Config& cfg, int32_t n, co
       if (lv == 0) a.mode = p.upsample ? kSrcUpsample : kSrcImage;
       else if (lv == 1 && k > 0) a.mode = kSrcDown;
       else a.mode = kSrcLevel;
+      // storage of the level written and of its source level
+      const LayoutCfg lc = layout_cfg(p);
+      const int es_d = level_es(lc, k);
+      const int es_s = lv == 0 ? 4 : level_es(lc, a.mode == kSrcDown ? k - 1 : k);
+      a.st = es_d == 4 ? 0 : (es_s == 4 ? 1 : 2);
       std::memcpy(a.taps, t.g, sizeof(float) * (2 * t.radius + 1));
       // algorithmic bytes: the source read once (input pixels for the first
       // level), the level written once, plus level 0 written when subsampling
-      double bytes = 8.0 * plan.pixels[k];
+      double bytes = (double)(es_s + es_d) * plan.pixels[k];
       if (lv == 0 && p.upsample) bytes = 4.0 * plan.pixels[k] + 4.0 * plan.input_px;
-      if (a.mode == kSrcDown) bytes += 4.0 * plan.pixels[k];
+      if (a.mode == kSrcDown) bytes += (double)es_d * plan.pixels[k];
       char label[32];
       std::snprintf(label, sizeof label, "o%d l%d R%d", k + p.o0, lv, t.radius);
       // a vertical and a horizontal pass of 2R + 1 taps per output pixel
@@ -591,10 +599,14 @@ sift_status launch_stages(const sift_handle* h, const Config& cfg, int32_t n, co
   }
   // detection and ordered compaction
   int64_t all_px = 0;
-  for (int k = 0; k < p.n_oct; ++k) all_px += plan.pixels[k];
+  double level_px_bytes = 0.0;
+  for (int k = 0; k < p.n_oct; ++k) {
+    all_px += plan.pixels[k];
+    level_px_bytes += (double)level_es(layout_cfg(p), k) * plan.pixels[k];
+  }
   const int bands = (int)plan.bands;
   // detection reads the s+3 levels once and writes one mask bit per pixel-layer
-  prec = prof_begin(kStDetect, (4.0 * (p.s + 3) + p.s / 8.0) * all_px, stream);
+  prec = prof_begin(kStDetect, (p.s + 3) * level_px_bytes + p.s / 8.0 * all_px, stream);
   if (bands > 0 && (st = check_hip(launch_detect(ws, hp, n, p, bands, stream), "detect")) != SIFT_OK)
     return st;
   prof_end(prec, stream);
@@ -942,6 +954,18 @@ sift_status sift_workspace_level(const sift_handle* h, int32_t height, int32_t w
   *level_height = ov.h;
   *level_width = ov.w;
   *level_pitch = ov.pitch;
+  return SIFT_OK;
+}
+
+sift_status sift_workspace_level_bytes(const sift_handle* h, int32_t height, int32_t width,
+                                      int32_t octave, int32_t* elem_bytes) {
+  if (!h || !elem_bytes) return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  sift_status st = validate_size(h, height, width);
+  if (st != SIFT_OK) return st;
+  const DevParams& d = cfg_for(h, height, width).dev;
+  const int k = octave - d.o0;
+  if (k < 0 || k >= d.n_oct) return fail(SIFT_ERR_INVALID_ARG, "no octave %d", octave);
+  *elem_bytes = level_es(layout_cfg(d), k);
   return SIFT_OK;
 }
 

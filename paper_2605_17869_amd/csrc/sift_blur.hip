@@ -45,7 +45,10 @@ constexpr int lds_stride4(int n) {
 
 // UP selects the source of level 0 of the upsampled octave (bilinear 2x of
 // the input image); otherwise a source pixel is src[y * sp + (x << csh)] - bias.
-template <int R, bool UP>
+// ST is the storage of source and destination level: 0 fp32 -> fp32, 1 fp32
+// -> fp16 (the first level of the second octave under fp16 storage), 2 fp16 ->
+// fp16; arithmetic is fp32 throughout, fp16 stores round to nearest even.
+template <int R, bool UP, int ST>
 __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
   constexpr int TW = kTileW;          // output columns of the strip
   constexpr int NT = kBlurThreads;
@@ -59,6 +62,9 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
   constexpr int NH = (2 * R + HB + 3) / 4;   // float4 reads per horizontal task
   static_assert(NREP * NT == NQ * B, "whole horizontal tasks per thread");
   static_assert(WI <= NT, "one source column per thread");
+  static_assert(!UP || ST == 0, "the input image is fp32");
+  constexpr bool S16 = ST == 2, D16 = ST >= 1;
+  constexpr uint32_t ES_S = S16 ? 2u : 4u, ES_D = D16 ? 2u : 4u;   // bytes per element
   __shared__ __align__(16) float s_v[2][B * SS];
 
   const int* tp = a.tile_prefix;
@@ -96,17 +102,17 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
     bias = kCentre;
   } else if (mode == kSrcLevel) {
     src = level_ptr(a.ws, e, ov, a.dst_level - 1);
-    sp = 4 * (int64_t)pk;
+    sp = ES_S * (int64_t)pk;
     csh = 0;
   } else {
     // level s of the previous octave at every second row and column
     const OctView pv = octave_view(e.h, e.w, lc, k - 1);
     src = level_ptr(a.ws, e, pv, a.p.s);
-    sp = 8 * (int64_t)pv.pitch;
+    sp = 2 * ES_S * (int64_t)pv.pitch;
     csh = 1;
   }
   const gchar* gsrc = uniform_ptr(reinterpret_cast<const gchar*>(as_global(src)));
-  const uint32_t bo = (uint32_t)(xc << csh) * 4u;
+  const uint32_t bo = (uint32_t)(xc << csh) * ES_S;
   // bilinear 2x upsampling: U[y][x] = I(y/2, x/2), the sample past the last
   // row or column clamped to it; computed on centred values
   const uint32_t ua = (uint32_t)(xc >> 1) * 4u, ub = (uint32_t)min((xc >> 1) + 1, e.w - 1) * 4u;
@@ -126,7 +132,11 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
       bot = uo ? (bot + (vd - bias)) * 0.5f : bot;
       return (y & 1) ? (top + bot) * 0.5f : top;
     } else {
-      return load_at(uniform_ptr(gsrc + y * sp), bo) - bias;
+      const float v = load_lv<S16>(uniform_ptr(gsrc + y * sp), bo) - bias;
+      // an fp32 level feeding an fp16 octave: its subsampled rows are that
+      // octave's level 0, which is stored in fp16, and level 1 is blurred from
+      // the stored values
+      return ST == 1 ? (float)(_Float16)v : v;
     }
   };
   // n consecutive rows from image row ybase (mirrored at the borders)
@@ -178,7 +188,7 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
   if (!UP && mode == kSrcDown)
     l0 = uniform_ptr(reinterpret_cast<gchar*>(as_global(level_ptr(a.ws, e, ov, 0))));
   const bool own_col = t >= R && t < R + TW && xs < wk;
-  const int64_t pkb = 4 * (int64_t)pk;
+  const int64_t pkb = ES_D * (int64_t)pk;
   const int M = cdiv(y1 - y0, B);     // steps
 
   for (int m = 0; m < M; ++m) {
@@ -189,7 +199,7 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
       // that owns the row and the strip that owns the column
 #pragma unroll
       for (int r = 0; r < B; ++r)
-        if (yb + r < y1) store_at(uniform_ptr(l0 + (yb + r) * pkb), (uint32_t)xs * 4u, w[R + r]);
+        if (yb + r < y1) store_lv<D16>(uniform_ptr(l0 + (yb + r) * pkb), (uint32_t)xs * ES_D, w[R + r]);
     }
     // vertical pass into LDS block m & 1 (threads past the strip's source
     // columns have nothing to write: their row offset would run past SS)
@@ -235,11 +245,11 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
         if (xo + HB <= wk) {
           // consecutive dwords: the compiler merges them into one wide store
 #pragma unroll
-          for (int j = 0; j < HB; ++j) store_at(row, (uint32_t)(xo + j) * 4u, acc[j]);
+          for (int j = 0; j < HB; ++j) store_lv<D16>(row, (uint32_t)(xo + j) * ES_D, acc[j]);
         } else {
 #pragma unroll
           for (int j = 0; j < HB; ++j)
-            if (xo + j < wk) store_at(row, (uint32_t)(xo + j) * 4u, acc[j]);
+            if (xo + j < wk) store_lv<D16>(row, (uint32_t)(xo + j) * ES_D, acc[j]);
         }
       }
     }
@@ -253,10 +263,13 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
 
 typedef void (*BlurKernel)(BlurArgs);
 
-#define SIFT_BLUR_CASE(RR) \
-  case RR: return up ? k_blur<RR, true> : k_blur<RR, false>;
+#define SIFT_BLUR_CASE(RR)                                                   \
+  case RR:                                                                   \
+    return up ? k_blur<RR, true, 0>                                          \
+              : (st == 0 ? k_blur<RR, false, 0>                              \
+                         : (st == 1 ? k_blur<RR, false, 1> : k_blur<RR, false, 2>));
 
-static BlurKernel blur_kernel(int radius, bool up) {
+static BlurKernel blur_kernel(int radius, bool up, int st) {
   switch (radius) {
     SIFT_BLUR_CASE(1) SIFT_BLUR_CASE(2) SIFT_BLUR_CASE(3) SIFT_BLUR_CASE(4)
     SIFT_BLUR_CASE(5) SIFT_BLUR_CASE(6) SIFT_BLUR_CASE(7) SIFT_BLUR_CASE(8)
@@ -270,7 +283,9 @@ static BlurKernel blur_kernel(int radius, bool up) {
 #undef SIFT_BLUR_CASE
 
 hipError_t launch_blur(const BlurArgs& a, int radius, int grid, hipStream_t stream) {
-  BlurKernel fn = blur_kernel(radius, a.mode == kSrcUpsample);
+  if (a.st < 0 || a.st > 2 || (a.st != 0 && (a.mode == kSrcUpsample || a.mode == kSrcImage)))
+    return hipErrorInvalidValue;
+  BlurKernel fn = blur_kernel(radius, a.mode == kSrcUpsample, a.st);
   if (!fn || a.th % kBlurRows != 0) return hipErrorInvalidValue;
   return launch(fn, dim3(grid), dim3(kBlurThreads), stream, a);
 }

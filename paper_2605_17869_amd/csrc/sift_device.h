@@ -44,6 +44,17 @@ __device__ __forceinline__ const float* level_ptr(char* ws, const ImgEntry& e, c
   return reinterpret_cast<const float*>(ws + e.region + ov.level0 + (int64_t)level * ov.plane);
 }
 
+// Element idx of a level stored as fp32 (H16 false) or fp16 (H16 true).
+template <bool H16>
+__device__ __forceinline__ float lv_at(const void* base, int64_t idx) {
+  if (H16) return (float)reinterpret_cast<const _Float16*>(base)[idx];
+  return reinterpret_cast<const float*>(base)[idx];
+}
+// The same with the storage known only at run time.
+__device__ __forceinline__ float lv_at(const void* base, int64_t idx, bool h16) {
+  return h16 ? lv_at<true>(base, idx) : lv_at<false>(base, idx);
+}
+
 // Inclusive sum of an int over the 64 lanes of a wave (exact, any order).
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = threadIdx.x & 63;
@@ -165,6 +176,18 @@ __device__ __forceinline__ float load_at(const gchar* row, uint32_t byte_off) {
 }
 __device__ __forceinline__ void store_at(gchar* row, uint32_t byte_off, float v) {
   *reinterpret_cast<gfloat*>(row + byte_off) = v;
+}
+typedef __attribute__((address_space(1))) _Float16 ghalf;
+// fp32 or fp16 (H16) element at a byte offset; stores round to nearest even
+template <bool H16>
+__device__ __forceinline__ float load_lv(const gchar* row, uint32_t byte_off) {
+  if (H16) return (float)*reinterpret_cast<const ghalf*>(row + byte_off);
+  return *reinterpret_cast<const gfloat*>(row + byte_off);
+}
+template <bool H16>
+__device__ __forceinline__ void store_lv(gchar* row, uint32_t byte_off, float v) {
+  if (H16) *reinterpret_cast<ghalf*>(row + byte_off) = (_Float16)v;
+  else *reinterpret_cast<gfloat*>(row + byte_off) = v;
 }
 
 // ---------------------------------------------------------------------------

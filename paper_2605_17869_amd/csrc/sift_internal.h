@@ -61,7 +61,11 @@ struct LayoutCfg {
   int s;          // n_scales
   int border;
   int max_cand;
+  int h16;        // 1: octaves after the first hold fp16 levels
 };
+
+// Bytes per stored level element of octave k.
+SIFT_HD int level_es(const LayoutCfg& c, int k) { return (c.h16 && k >= 1) ? 2 : 4; }
 
 SIFT_HD int bands_of(int hk, int border) {
   int rows = hk - 2 * border;
@@ -80,6 +84,7 @@ SIFT_HD int segs_of(int wk, int border) {
 // refined records, orientations, keypoint offsets).
 struct OctView {
   int h, w, pitch;         // size and row pitch (elements) of the octave
+  int es;                  // bytes per level element: 4 (fp32) or 2 (fp16)
   int nseg, nband;         // detection segments per row, bands of kBand rows
   int band_base;           // first band of this octave within the image
   int64_t level0;          // Gaussian level 0; level j at level0 + j * plane
@@ -108,12 +113,14 @@ SIFT_HD void region_walk(int h, int w, const LayoutCfg& c, int want, OctView* v,
     int hk, wk;
     octave_dims(h, w, c.upsample, k, &hk, &wk);
     const int pitch = level_pitch(wk);
-    const int64_t plane = align_up((int64_t)pitch * hk * 4, 256);
+    const int es = level_es(c, k);
+    const int64_t plane = align_up((int64_t)pitch * hk * es, 256);
     const int nb = bands_of(hk, c.border);
     if (v && k == want) {
       v->h = hk;
       v->w = wk;
       v->pitch = pitch;
+      v->es = es;
       v->plane = plane;
       v->level0 = off;
       v->nseg = segs_of(wk, c.border);
@@ -236,7 +243,7 @@ SIFT_HD void make_header(int n, Header* hd) {
 // Settings the kernels read (a by-value kernel argument).
 struct DevParams {
   int n_oct, o0, s, upsample, border, refine_iters, upright, rootsift;
-  int max_kp, max_cand, n_dsp, pad0;
+  int max_kp, max_cand, n_dsp, h16;
   float sigma0, contrast_thr, pre_thr, edge_ratio;
   float ori_sigma_factor, ori_radius_factor, ori_peak_ratio;
   float desc_magnif, desc_clamp;
@@ -250,6 +257,7 @@ SIFT_HD LayoutCfg layout_cfg(const DevParams& p) {
   c.s = p.s;
   c.border = p.border;
   c.max_cand = p.max_cand;
+  c.h16 = p.h16;
   return c;
 }
 
@@ -276,6 +284,7 @@ struct BlurArgs {
   int dst_level;    // level written
   int mode;         // BlurSrc
   int th;           // chunk height (64, 128, 256 or 512 rows)
+  int st;           // storage: 0 fp32 -> fp32, 1 fp32 -> fp16, 2 fp16 -> fp16
   DevParams p;
   float taps[2 * kMaxRadius + 1];
 };

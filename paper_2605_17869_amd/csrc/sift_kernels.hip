@@ -83,11 +83,11 @@ struct DetRow {
   float own[S + 2], mx3[S + 2], mn3[S + 2], lrmx[S + 2], lrmn[S + 2];
 };
 
-template <int S>
-__device__ __forceinline__ void det_load_row(DetRow<S>& d, const float* const* L, int64_t off) {
+template <int S, bool H16>
+__device__ __forceinline__ void det_load_row(DetRow<S>& d, const char* const* L, int64_t off) {
   float lv[S + 3];
 #pragma unroll
-  for (int j = 0; j < S + 3; ++j) lv[j] = L[j][off];
+  for (int j = 0; j < S + 3; ++j) lv[j] = lv_at<H16>(L[j], off);
 #pragma unroll
   for (int j = 0; j < S + 2; ++j) {
     const float v = lv[j + 1] - lv[j];
@@ -101,44 +101,22 @@ __device__ __forceinline__ void det_load_row(DetRow<S>& d, const float* const* L
   }
 }
 
-template <int S>
-__global__ __launch_bounds__(kDetectWaves * 64) void k_detect(char* ws, HdrPtrs hp, int n,
-                                                             DevParams p) {
-  __shared__ int s_cnt[kDetectWaves][S];
-  const int* bp = hp.band_prefix;
-  const int item = blockIdx.x;
-  if (item >= bp[n]) return;   // a grid sized for larger images than the table's
-  const int img = find_owner(bp, n, item);
-  const int lb = item - bp[img];
-  const ImgEntry e = hp.table[img];
-  const LayoutCfg lc = layout_cfg(p);
-  int k, band;
-  band_owner(e.h, e.w, lc, lb, &k, &band);
-  const OctView ov = octave_view(e.h, e.w, lc, k);
-  const int hk = ov.h, wk = ov.w, pk = ov.pitch, nseg = ov.nseg;
-  const int b = p.border;
-  const int r_begin = b + band * kBand;
-  const int r_end = min(r_begin + kBand, hk - b);
-  const float* L[S + 3];
-#pragma unroll
-  for (int j = 0; j < S + 3; ++j) L[j] = level_ptr(ws, e, ov, j);
-  unsigned long long* masks = reinterpret_cast<unsigned long long*>(ws + e.region + ov.masks);
+// The rows of one band: per-layer candidate counts into cnt.  H16: the
+// octave's levels are stored as fp16.
+template <int S, bool H16>
+__device__ __forceinline__ void detect_band(const char* const* L, unsigned long long* masks,
+                                            int hk, int wk, int pk, int nseg, int b, int r_begin,
+                                            int r_end, float thr, int* cnt) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const float thr = p.pre_thr;
-
-  int cnt[S];
-#pragma unroll
-  for (int i = 0; i < S; ++i) cnt[i] = 0;
-
   for (int sg = wave; sg < nseg; sg += kDetectWaves) {
     const int c = b + sg * kSeg + lane - 1;
     const int cl = min(c, wk - 1);
     const bool out_col = lane >= 1 && lane <= kSeg && c < wk - b;
     DetRow<S> w0, w1, w2;
-    det_load_row<S>(w0, L, (int64_t)(r_begin - 1) * pk + cl);
-    det_load_row<S>(w1, L, (int64_t)r_begin * pk + cl);
+    det_load_row<S, H16>(w0, L, (int64_t)(r_begin - 1) * pk + cl);
+    det_load_row<S, H16>(w1, L, (int64_t)r_begin * pk + cl);
     for (int r = r_begin; r < r_end; ++r) {
-      det_load_row<S>(w2, L, (int64_t)(r + 1) * pk + cl);
+      det_load_row<S, H16>(w2, L, (int64_t)(r + 1) * pk + cl);
       float max9[S + 2], min9[S + 2];
 #pragma unroll
       for (int j = 0; j < S + 2; ++j) {
@@ -161,6 +139,42 @@ __global__ __launch_bounds__(kDetectWaves * 64) void k_detect(char* ws, HdrPtrs 
       w1 = w2;
     }
   }
+}
+
+// H16MODE: fp16 level storage is on (the first octave stays fp32, so each
+// work-group picks its octave's path).
+template <int S, bool H16MODE>
+__global__ __launch_bounds__(kDetectWaves * 64) void k_detect(char* ws, HdrPtrs hp, int n,
+                                                             DevParams p) {
+  __shared__ int s_cnt[kDetectWaves][S];
+  const int* bp = hp.band_prefix;
+  const int item = blockIdx.x;
+  if (item >= bp[n]) return;   // a grid sized for larger images than the table's
+  const int img = find_owner(bp, n, item);
+  const int lb = item - bp[img];
+  const ImgEntry e = hp.table[img];
+  const LayoutCfg lc = layout_cfg(p);
+  int k, band;
+  band_owner(e.h, e.w, lc, lb, &k, &band);
+  const OctView ov = octave_view(e.h, e.w, lc, k);
+  const int hk = ov.h, wk = ov.w, pk = ov.pitch, nseg = ov.nseg;
+  const int b = p.border;
+  const int r_begin = b + band * kBand;
+  const int r_end = min(r_begin + kBand, hk - b);
+  const char* L[S + 3];
+#pragma unroll
+  for (int j = 0; j < S + 3; ++j) L[j] = reinterpret_cast<const char*>(level_ptr(ws, e, ov, j));
+  unsigned long long* masks = reinterpret_cast<unsigned long long*>(ws + e.region + ov.masks);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float thr = p.pre_thr;
+
+  int cnt[S];
+#pragma unroll
+  for (int i = 0; i < S; ++i) cnt[i] = 0;
+  if (H16MODE && ov.es == 2)
+    detect_band<S, true>(L, masks, hk, wk, pk, nseg, b, r_begin, r_end, thr, cnt);
+  else
+    detect_band<S, false>(L, masks, hk, wk, pk, nseg, b, r_begin, r_end, thr, cnt);
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < S; ++i) s_cnt[wave][i] = cnt[i];
@@ -328,12 +342,13 @@ __global__ __launch_bounds__(256) void k_refine(char* ws, HdrPtrs hp, int n, Dev
       for (int a = 0; a < 3; ++a) {
         const float* La = level_ptr(ws, e, ov, li - 1 + a);
         const float* Lb = level_ptr(ws, e, ov, li + a);
+        const bool h16 = ov.es == 2;
 #pragma unroll
         for (int dr = 0; dr < 3; ++dr)
 #pragma unroll
           for (int dc = 0; dc < 3; ++dc) {
             const int64_t off = (int64_t)(r - 1 + dr) * pk + (c - 1 + dc);
-            d[a][dr][dc] = (double)(Lb[off] - La[off]);
+            d[a][dr][dc] = (double)(lv_at(Lb, off, h16) - lv_at(La, off, h16));
           }
       }
       v = d[1][1][1];
@@ -400,6 +415,8 @@ __global__ __launch_bounds__(256) void k_refine(char* ws, HdrPtrs hp, int n, Dev
 // max gives an orientation refined by a parabola through the bin and its two
 // neighbours.
 
+// H16MODE: fp16 level storage is on; each keypoint's octave picks the path.
+template <bool H16MODE>
 __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, DevParams p) {
   // OC histogram columns per wave: lanes l, l + OC, ... share column l % OC
   // and add in turn (each group with instructions of its own)
@@ -460,11 +477,19 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
         ddx[u] = dx;
         ddy[u] = dy;
         // samples that do not contribute read the (interior) centre instead
-        const float* row = L + (int64_t)(ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c);
-        ga[u] = row[1];
-        gb[u] = row[-1];
-        gc[u] = row[pk];
-        gd[u] = row[-pk];
+        const int64_t at = (int64_t)(ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c);
+        if (H16MODE && ov.es == 2) {
+          ga[u] = lv_at<true>(L, at + 1);
+          gb[u] = lv_at<true>(L, at - 1);
+          gc[u] = lv_at<true>(L, at + pk);
+          gd[u] = lv_at<true>(L, at - pk);
+        } else {
+          const float* row = L + at;
+          ga[u] = row[1];
+          gb[u] = row[-1];
+          gc[u] = row[pk];
+          gd[u] = row[-pk];
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -579,7 +604,8 @@ __global__ __launch_bounds__(256) void k_ori_scan(char* ws, HdrPtrs hp, int n, D
 
 // ND: the number of domain sizes the code is unrolled for (1, or the most).
 // The bound of 16 resident groups per CU caps registers at 128 per lane.
-template <int ND>
+// H16MODE: fp16 level storage is on; each keypoint's octave picks the path.
+template <int ND, bool H16MODE>
 __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n, DevParams p) {
   // DC histogram columns: lanes l, l + DC, ... share column l % DC and add
   // in turn.  Four lanes per column with one domain size; with several, two
@@ -781,11 +807,20 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
                 in_window(xr0 * inv_max, yr0 * inv_max);
         sxy[u] = (dy << 16) | (dx & 0xffff);
         // samples that do not contribute read the (interior) centre instead
-        const uint32_t at = (uint32_t)((ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c)) * 4u;
-        ga[u] = load_at(gL, at + 4u);
-        gb[u] = load_at(gL, at - 4u);
-        gc[u] = load_at(gL, at + pkb);
-        gd[u] = load_at(gL, at - pkb);
+        const uint32_t idx = (uint32_t)((ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c));
+        if (H16MODE && ov.es == 2) {
+          const uint32_t at = idx * 2u, pkh = (uint32_t)pk * 2u;
+          ga[u] = load_lv<true>(gL, at + 2u);
+          gb[u] = load_lv<true>(gL, at - 2u);
+          gc[u] = load_lv<true>(gL, at + pkh);
+          gd[u] = load_lv<true>(gL, at - pkh);
+        } else {
+          const uint32_t at = idx * 4u;
+          ga[u] = load_at(gL, at + 4u);
+          gb[u] = load_at(gL, at - 4u);
+          gc[u] = load_at(gL, at + pkb);
+          gd[u] = load_at(gL, at - pkb);
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -875,15 +910,18 @@ hipError_t launch_finalize(const HdrPtrs& hp, int n, const DevParams& p, hipStre
 
 hipError_t launch_detect(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
                          hipStream_t stream) {
+#define SIFT_DETECT_CASE(SS)                                                              \
+  case SS:                                                                                \
+    return p.h16 ? launch(k_detect<SS, true>, dim3(grid), dim3(kDetectWaves * 64), stream, \
+                          ws, hp, n, p)                                                    \
+                 : launch(k_detect<SS, false>, dim3(grid), dim3(kDetectWaves * 64), stream, \
+                          ws, hp, n, p);
   switch (p.s) {
-    case 1: return launch(k_detect<1>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
-    case 2: return launch(k_detect<2>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
-    case 3: return launch(k_detect<3>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
-    case 4: return launch(k_detect<4>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
-    case 5: return launch(k_detect<5>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
-    case 6: return launch(k_detect<6>, dim3(grid), dim3(kDetectWaves * 64), stream, ws, hp, n, p);
+    SIFT_DETECT_CASE(1) SIFT_DETECT_CASE(2) SIFT_DETECT_CASE(3)
+    SIFT_DETECT_CASE(4) SIFT_DETECT_CASE(5) SIFT_DETECT_CASE(6)
     default: return hipErrorInvalidValue;
   }
+#undef SIFT_DETECT_CASE
 }
 
 hipError_t launch_band_scan(char* ws, const HdrPtrs& hp, int n, const DevParams& p,
@@ -908,7 +946,8 @@ hipError_t launch_refine(char* ws, const HdrPtrs& hp, int n, const DevParams& p,
 
 hipError_t launch_orient(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
                          hipStream_t stream) {
-  return launch(k_orient, dim3(grid), dim3(256), stream, ws, hp, n, p);
+  return p.h16 ? launch(k_orient<true>, dim3(grid), dim3(256), stream, ws, hp, n, p)
+               : launch(k_orient<false>, dim3(grid), dim3(256), stream, ws, hp, n, p);
 }
 
 hipError_t launch_ori_scan(char* ws, const HdrPtrs& hp, int n, const DevParams& p,
@@ -920,10 +959,14 @@ hipError_t launch_describe(char* ws, const HdrPtrs& hp, int n, const DevParams& 
                          hipStream_t stream) {
   // the smallest unrolled size count that covers n_dsp (5: the paper's
   // pooling set, 10: the linearly spaced set of its benchmark)
-  if (p.n_dsp == 1) return launch(k_describe<1>, dim3(grid), dim3(64), stream, ws, hp, n, p);
-  if (p.n_dsp <= 5) return launch(k_describe<5>, dim3(grid), dim3(64), stream, ws, hp, n, p);
-  if (p.n_dsp <= 10) return launch(k_describe<10>, dim3(grid), dim3(64), stream, ws, hp, n, p);
-  return launch(k_describe<kMaxDsp>, dim3(grid), dim3(64), stream, ws, hp, n, p);
+#define SIFT_DESCRIBE(NDD)                                                         \
+  return p.h16 ? launch(k_describe<NDD, true>, dim3(grid), dim3(64), stream, ws, hp, n, p) \
+               : launch(k_describe<NDD, false>, dim3(grid), dim3(64), stream, ws, hp, n, p)
+  if (p.n_dsp == 1) SIFT_DESCRIBE(1);
+  if (p.n_dsp <= 5) SIFT_DESCRIBE(5);
+  if (p.n_dsp <= 10) SIFT_DESCRIBE(10);
+  SIFT_DESCRIBE(kMaxDsp);
+#undef SIFT_DESCRIBE
 }
 
 }  // namespace sift

@@ -40,6 +40,7 @@ class SiftParams(ctypes.Structure):
         ("rootsift", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
         ("max_candidates", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
         ("n_streams", ctypes.c_int32), ("upsample_max_pixels", ctypes.c_int32),
+        ("pyramid_fp16", ctypes.c_int32),
     ]
 
 
@@ -119,6 +120,8 @@ _SIGNATURES = {
                                             ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]),
+    "sift_workspace_level_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "sift_profile_start": (ctypes.c_int, []),
     "sift_profile_stop": (ctypes.c_int, [ctypes.POINTER(SiftStageStat), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32)]),
@@ -499,10 +502,14 @@ class Extractor:
                                              ctypes.byref(ptr), ctypes.byref(lh),
                                              ctypes.byref(lw), ctypes.byref(lp)),
                "sift_workspace_level")
+        es = ctypes.c_int32()
+        _check(self.lib.sift_workspace_level_bytes(self.handle, height, width, octave,
+                                                   ctypes.byref(es)), "sift_workspace_level_bytes")
         off = ptr.value - workspace.data_ptr()
         n = lh.value * lp.value
-        flat = workspace[off:off + 4 * n].view(torch.float32)
-        arr = flat.view(lh.value, lp.value)[:, :lw.value].cpu().numpy().astype(np.float64)
+        dt = torch.float16 if es.value == 2 else torch.float32
+        flat = workspace[off:off + es.value * n].view(dt)
+        arr = flat.view(lh.value, lp.value)[:, :lw.value].float().cpu().numpy().astype(np.float64)
         return arr + 0.5
 
 

@@ -103,7 +103,7 @@ def check_order(oracle_result, kps, rep: Report, margin: float = MARGIN, before=
 
 
 def compare(oracle_result, kps, desc, params, oracle_mod, margin: float = MARGIN,
-            sample: set | None = None, before=None) -> Report:
+            sample: set | None = None, before=None, tol: dict | None = None) -> Report:
     """Compare keypoints ``kps`` (structured array with the oracle's field
     names) and descriptors ``desc`` with ``oracle_result``, including their
     canonical order.
@@ -112,8 +112,11 @@ def compare(oracle_result, kps, desc, params, oracle_mod, margin: float = MARGIN
     large inputs where the oracle describes only some candidates).
     ``before``: only source keys below this one are compared (a capped output
     is the prefix of the canonical sequence up to its cut; see
-    ``compare_capped``).  Without it the check assumes no cap was hit."""
+    ``compare_capped``).  Without it the check assumes no cap was hit.
+    ``tol``: overrides of the value tolerances (keys xy, angle, desc, rel)."""
     rep = Report()
+    t = dict(xy=TOL_XY, angle=TOL_ANGLE, desc=TOL_DESC, rel=TOL_REL)
+    t.update(tol or {})
     got = group_by_source(kps)
     by_key = {(e["o"], e["i0"], e["r0"], e["c0"]): e for e in oracle_result.log}
     octs = {oc.o: oc for oc in oracle_result.octaves}
@@ -156,13 +159,13 @@ def compare(oracle_result, kps, desc, params, oracle_mod, margin: float = MARGIN
             rep.max_err_rel = max(rep.max_err_rel, er)
             rep.checked_keypoints += 1
             bad = []
-            if exy > TOL_XY:
+            if exy > t["xy"]:
                 bad.append(f"xy err {exy:.3g}")
-            if ea > TOL_ANGLE:
+            if ea > t["angle"]:
                 bad.append(f"angle err {ea:.3g}")
-            if ed > TOL_DESC:
+            if ed > t["desc"]:
                 bad.append(f"desc err {ed:.3g}")
-            if er > TOL_REL:
+            if er > t["rel"]:
                 bad.append(f"sigma/response rel err {er:.3g}")
             if bad:
                 rep.mismatches.append((key, ", ".join(bad)))
