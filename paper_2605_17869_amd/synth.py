@@ -245,3 +245,37 @@ def descriptor_sets(seed: int, n_a: int, n_b: int, n_common: int, noise: float =
     b[dst] = unit(a[src] + np.abs(rng.normal(0.0, noise, size=(n_common, dim))))
     truth = np.stack([src, dst], axis=1) if n_common else np.zeros((0, 2), dtype=np.int64)
     return a.astype(np.float32), b.astype(np.float32), truth.astype(np.int64)
+
+
+def homography_pairs(seed: int, n: int, outlier_frac: float = 0.3, noise: float = 0.5,
+                     size: tuple = (1066, 1600)) -> tuple:
+    """Seeded correspondences under a random homography: points uniform in an
+    H x W image, a random homography near a similarity (rotation U[0, 360),
+    scale U[0.5, 2], a small perspective term) about the image centre, inlier
+    targets perturbed by N(0, noise) px, outlier targets uniform in the image.
+    Returns (a, b, H, inlier_mask) as float64 / bool."""
+    rng = np.random.default_rng(seed)
+    h, w = size
+    a = np.stack([rng.uniform(0, w, n), rng.uniform(0, h, n)], axis=1)
+    ang = rng.uniform(0.0, 2.0 * math.pi)
+    sc = rng.uniform(0.5, 2.0)
+    cx, cy = (w - 1) / 2.0, (h - 1) / 2.0
+    c, s = math.cos(ang) * sc, math.sin(ang) * sc
+    H = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+    H[2, :2] = rng.uniform(-2e-4, 2e-4, 2)
+    T1 = np.array([[1.0, 0.0, -cx], [0.0, 1.0, -cy], [0.0, 0.0, 1.0]])
+    T2 = np.array([[1.0, 0.0, cx], [0.0, 1.0, cy], [0.0, 0.0, 1.0]])
+    H = T2 @ H @ T1
+    H /= H[2, 2]
+    ah = np.c_[a, np.ones(n)] @ H.T
+    b = ah[:, :2] / ah[:, 2:3] + rng.normal(0.0, noise, (n, 2))
+    out = rng.uniform(size=n) < outlier_frac
+    b[out] = np.stack([rng.uniform(0, w, out.sum()), rng.uniform(0, h, out.sum())], axis=1)
+    return a, b, H, ~out
+
+
+def sample_numbers(seed: int, k: int = 1500) -> np.ndarray:
+    """The random numbers a verification draws its k minimal samples from:
+    k x 4 float32 values in [0, 1)."""
+    rng = np.random.default_rng(seed)
+    return rng.random((k, 4), dtype=np.float32)
