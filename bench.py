@@ -185,6 +185,49 @@ def match_bench(n_pairs: int, n_a: int, n_b: int, reps: int = 20):
             "data": "seeded descriptor sets: 3/4 of the rows noisy copies, the rest fresh"}
 
 
+def verify_bench(n_pairs: int = 32, n_corr: int = 1300, n_hyp: int = 1500, reps: int = 20):
+    """Verification of n_pairs seeded correspondence sets (n_corr each, 40 %
+    outliers, 0.7 px noise) with n_hyp hypotheses per pair, in one
+    sift_verify_batch call."""
+    import torch
+    import paper_2605_17869_amd as sm
+    dev = torch.device("cuda:0")
+    pairs = []
+    for k in range(n_pairs):
+        a, b, _, _ = synth.homography_pairs(800_000 + k, n_corr, 0.4, 0.7)
+        ka = np.zeros((n_corr, 12), np.int32)
+        kb = np.zeros((n_corr, 12), np.int32)
+        ka.view(np.float32)[:, 0:2] = a
+        kb.view(np.float32)[:, 0:2] = b
+        m = np.zeros((n_corr, 4), np.int32)
+        m[:, 0] = m[:, 1] = np.arange(n_corr)
+        pairs.append((torch.from_numpy(ka).to(dev), torch.from_numpy(kb).to(dev),
+                      torch.from_numpy(m).to(dev), None))
+    u = torch.from_numpy(synth.sample_numbers(810_000, n_hyp)).to(dev)
+    stream = torch.cuda.current_stream()
+    outs = sm.verify_batch(pairs, u, stream=stream)
+    ws = outs[0]._ws
+    first = [o.host() for o in outs]
+    for _ in range(3):
+        sm.verify_batch(pairs, u, workspace=ws, stream=stream, outs=outs)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        sm.verify_batch(pairs, u, workspace=ws, stream=stream, outs=outs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    again = [o.host() for o in outs]
+    same = all(x[0].tobytes() == y[0].tobytes() for x, y in zip(first, again))
+    return {"pairs": n_pairs, "correspondences_per_pair": n_corr, "hypotheses_per_pair": n_hyp,
+            "ms_per_call": round(ms, 4), "pairs_per_s": round(n_pairs / (ms * 1e-3), 1),
+            "residuals_per_s": round(n_pairs * n_hyp * n_corr / (ms * 1e-3), 1),
+            "mean_inliers": round(float(np.mean([x[2] for x in again])), 1),
+            "bitwise_identical_reruns": same,
+            "data": "seeded correspondences under random homographies, 40 % outliers"}
+
+
 def serve_points(unique_images: int, requests: int, warmup_requests: int, fractions,
                  one_at_a_time: bool):
     """Serving: requests arrive as a Poisson process at fractions of the
@@ -583,6 +626,7 @@ def main():
     matching = None
     if not args.no_match:
         matching = match_bench(32, 2000, 2000)
+        matching["verification"] = verify_bench()
 
     mpix = sum(h * w for h, w in sizes) / 1e6
     n_kp = int(sum(len(b[0]) for b in batch_host))

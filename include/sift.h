@@ -491,6 +491,57 @@ sift_status sift_match_workspace_size(int32_t n, const sift_match_pair* pairs, s
 sift_status sift_match_batch(int32_t n, const sift_match_pair* pairs, float ratio,
                              void* d_workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * Geometric verification of matched pairs: the estimator after matching
+ * (Section 3.6, "GPU MAGSAC++": many minimal-sample hypotheses solved in one
+ * batch, scored by soft marginalisation), as a planar homography, for many
+ * pairs in one launch sequence.  All arithmetic is fp64.
+ *
+ * For a pair, the correspondences are the first *n_matches records of
+ * `matches` (sift_match_batch output: query indexes kp_a, train kp_b), their
+ * keypoint positions in pixels.  Each point set is normalised (mean to 0, mean
+ * distance to sqrt 2).  Hypothesis k (k < n_hyp) takes correspondences
+ * floor(u[k][j] * N), j = 0..3, from the caller's numbers d_samples
+ * [n_hyp][4] in [0, 1) (device; the same numbers serve every pair), and
+ * solves the 4-point DLT system (h33 = 1) by Gaussian elimination with partial
+ * pivoting; repeated indices or a pivot below 1e-12 of the largest entry give
+ * no hypothesis.  A correspondence with transfer residual r (pixels in image
+ * b) counts w(r) = sqrt(pi/2) / sigma_max * (erf(tau / sqrt 2) - erf(r /
+ * (sqrt 2 sigma_max))) for r < tau * sigma_max, tau = sqrt(2 ln 100), else 0:
+ * the likelihood of a Rayleigh residual truncated at its 0.99 quantile,
+ * marginalised over a noise scale uniform on (0, sigma_max].  The hypothesis
+ * of largest summed w (first among equals) is refined by at most refine_iters
+ * steps of reweighted least squares on the normalised DLT rows, each kept only
+ * if it raises the score.  Outputs (device): H[9] row-major with h33 = 1 (NaN
+ * when there is no hypothesis, e.g. fewer than 4 correspondences), *score,
+ * *n_inliers (w > 0), *best (hypothesis index or -1; may be NULL), weights[cap]
+ * (final w per correspondence, 0 past N; may be NULL).  Bit-identical run to
+ * run.  sift_verify_workspace_size sizes the workspace; sift_verify_batch only
+ * enqueues.  Errors: INVALID_ARG (null pointers, cap beyond 65536, n_hyp
+ * beyond 65536, sigma_max <= 0), WORKSPACE_TOO_SMALL, HIP.
+ */
+typedef struct {
+  const sift_keypoint* kp_a;
+  const sift_keypoint* kp_b;
+  const sift_match* matches;
+  const int32_t* n_matches;
+  int32_t cap;
+  double* H;
+  double* score;
+  int32_t* n_inliers;
+  int32_t* best;
+  float* weights;
+} sift_verify_pair;
+
+#define SIFT_VERIFY_MAX_PAIRS 4096
+#define SIFT_VERIFY_MAX_HYPOTHESES 65536
+
+sift_status sift_verify_workspace_size(int32_t n, const sift_verify_pair* pairs, int32_t n_hyp,
+                                       size_t* bytes);
+sift_status sift_verify_batch(int32_t n, const sift_verify_pair* pairs, const float* d_samples,
+                              int32_t n_hyp, float sigma_max, int32_t refine_iters,
+                              void* d_workspace, size_t workspace_bytes, void* stream);
+
 const char* sift_status_string(sift_status st);
 /* Detail of the last error on the calling thread ("" if none). */
 const char* sift_last_error(void);

@@ -83,6 +83,13 @@ class SiftMatchPair(ctypes.Structure):
                 ("n_found", ctypes.c_void_p), ("capacity", ctypes.c_int32)]
 
 
+class SiftVerifyPair(ctypes.Structure):
+    _fields_ = [("kp_a", ctypes.c_void_p), ("kp_b", ctypes.c_void_p), ("matches", ctypes.c_void_p),
+                ("n_matches", ctypes.c_void_p), ("cap", ctypes.c_int32), ("H", ctypes.c_void_p),
+                ("score", ctypes.c_void_p), ("n_inliers", ctypes.c_void_p),
+                ("best", ctypes.c_void_p), ("weights", ctypes.c_void_p)]
+
+
 MATCH_DTYPE = np.dtype([("query", "<i4"), ("train", "<i4"), ("similarity", "<f4"),
                         ("distance", "<f4")])
 
@@ -203,6 +210,12 @@ _SIGNATURES = {
                                                     ctypes.POINTER(ctypes.c_int32),
                                                     ctypes.POINTER(ctypes.c_int32),
                                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "sift_verify_workspace_size": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(SiftVerifyPair),
+                                                  ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]),
+    "sift_verify_batch": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(SiftVerifyPair),
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_float,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                         ctypes.c_void_p]),
     "sift_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sift_last_error": (ctypes.c_char_p, []),
 }
@@ -760,3 +773,61 @@ def match_batch(pairs, ratio: float = 0.8, workspace=None, stream=None, outs=Non
 def match(desc_a, desc_b, ratio: float = 0.8, count_a=None, count_b=None, stream=None) -> Matches:
     """One pair: see ``match_batch``."""
     return match_batch([(desc_a, count_a, desc_b, count_b)], ratio=ratio, stream=stream)[0]
+
+
+@dataclass
+class Verification:
+    """Device-resident result of verifying one pair (torch tensors on the GPU)."""
+    H: object              # float64 [9], row-major, h33 = 1 (NaN: no hypothesis)
+    score: object          # float64 [1]
+    ints: object           # int32 [2]: n_inliers, best hypothesis (-1: none)
+    weights: object        # float32 [cap]: final weight per correspondence
+
+    def host(self):
+        """(H as a 3 x 3 numpy array, score, n_inliers, best, weights)."""
+        i = self.ints.cpu().numpy()
+        return (self.H.cpu().numpy().reshape(3, 3), float(self.score.cpu().item()), int(i[0]),
+                int(i[1]), self.weights.cpu().numpy())
+
+
+def verify_batch(pairs, samples, sigma_max: float = 2.0, refine_iters: int = 5, workspace=None,
+                 stream=None, outs=None) -> list:
+    """``sift_verify_batch`` over pairs of (kp_a, kp_b, matches, n_matches):
+    keypoint tensors as ``Features.keypoints`` (int32 [cap, 12]), matches as
+    ``Matches.records`` (int32 [cap, 4]) and n_matches a one-element int32
+    tensor (e.g. ``Matches.counters[0:1]``) or None for every row; ``samples``
+    a float32 CUDA tensor [n_hyp, 4] of numbers in [0, 1)."""
+    import torch
+    lib = load_library()
+    if samples.dim() != 2 or samples.shape[1] != 4 or samples.dtype != torch.float32 \
+            or not samples.is_cuda or not samples.is_contiguous():
+        raise ValueError("samples must be a contiguous float32 CUDA tensor [n_hyp, 4]")
+    n = len(pairs)
+    arr = (SiftVerifyPair * n)()
+    res = list(outs) if outs is not None else []
+    for i, (ka, kb, m, cnt) in enumerate(pairs):
+        cap = int(m.shape[0])
+        if outs is None:
+            res.append(Verification(torch.empty(9, dtype=torch.float64, device="cuda"),
+                                    torch.empty(1, dtype=torch.float64, device="cuda"),
+                                    torch.empty(2, dtype=torch.int32, device="cuda"),
+                                    torch.empty(max(cap, 1), dtype=torch.float32, device="cuda")))
+        v = res[i]
+        ib = v.ints.data_ptr()
+        arr[i] = SiftVerifyPair(ka.data_ptr(), kb.data_ptr(), m.data_ptr(),
+                                cnt.data_ptr() if cnt is not None else None, cap,
+                                v.H.data_ptr(), v.score.data_ptr(), ib, ib + 4,
+                                v.weights.data_ptr())
+    need = ctypes.c_size_t()
+    _check(lib.sift_verify_workspace_size(n, arr, int(samples.shape[0]), ctypes.byref(need)),
+           "sift_verify_workspace_size")
+    ws = workspace
+    if ws is None or ws.numel() * ws.element_size() < need.value:
+        ws = torch.empty(max(need.value, 256), dtype=torch.uint8, device="cuda")
+    _check(lib.sift_verify_batch(n, arr, ctypes.c_void_p(samples.data_ptr()), int(samples.shape[0]),
+                                 ctypes.c_float(sigma_max), refine_iters,
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                 _stream_handle(stream)), "sift_verify_batch")
+    for v in res:
+        v._ws = ws
+    return res
