@@ -107,6 +107,11 @@ typedef struct {
                                  all arithmetic stays fp32 and the first octave stays fp32
                                  (section 3.2, "GPU Pipeline Stages"): about half the pyramid
                                  bytes of those octaves, at fp16 accuracy for their keypoints */
+  int32_t blur_chain;         /* 0: library choice (2); 1: one launch per Gaussian level; 2..4: up
+                                 to that many consecutive levels of an octave blurred in one
+                                 launch (runs of radius <= 8 that the library has a kernel
+                                 for), so the levels between are not read back from memory.
+                                 Any value gives bit-identical results (tuning only) */
 } sift_params;
 
 /* One keypoint, 48 bytes.  Keypoints of an image come in canonical order:

@@ -59,18 +59,43 @@ def smem_misaligned(asm_text: str) -> list:
     return bad
 
 
+MIX_RE = re.compile(r"^\s+(v_(?:fma|mad)_mix\w*)\s")
+
+
+def mixed_f16_fma(asm_text: str) -> list:
+    """Mixed-precision fused multiply-adds (v_fma_mix*, v_mad_mix*).  The
+    compiler may fold an fp16 conversion into the fma that produced its input,
+    rounding the exact product-sum to fp16 once instead of the fp32 result; at
+    fp16 ties that gives the other neighbour, so levels stored in fp16 would
+    depend on how a kernel was compiled.  Returns [(kernel, line)]."""
+    bad, fn = [], None
+    for line in asm_text.splitlines():
+        m = re.match(r"^(_Z\w+):", line)
+        if m:
+            fn = m.group(1)
+        if MIX_RE.match(line):
+            bad.append((fn, line.strip()))
+    return bad
+
+
 def device_asm_cmd(src: Path, out: Path) -> list:
     return [hipcc(), "-x", "hip", *HIP_FLAGS, "--offload-device-only", "-S", str(src), "-o", str(out)]
 
 
 def check_smem(asm_files):
-    """Fail the build if any kernel has a misaligned scalar-memory immediate."""
-    problems = []
+    """Fail the build if any kernel has a misaligned scalar-memory immediate
+    or a mixed-precision fma."""
+    problems, mixed = [], []
     for path in asm_files:
-        problems += smem_misaligned(Path(path).read_text())
+        text = Path(path).read_text()
+        problems += smem_misaligned(text)
+        mixed += mixed_f16_fma(text)
     if problems:
         lines = "\n".join(f"  {fn}: {ins}" for fn, ins in problems[:20])
         raise RuntimeError(f"scalar memory access with a misaligned immediate offset:\n{lines}")
+    if mixed:
+        lines = "\n".join(f"  {fn}: {ins}" for fn, ins in mixed[:20])
+        raise RuntimeError(f"mixed-precision fma (an fp16 rounding folded into an fma):\n{lines}")
 
 
 def kernel_source_hash(names=("sift_blur.hip", "sift_device.h", "sift_internal.h")) -> str:

@@ -46,6 +46,8 @@ constexpr int kMaxBatch = 4096;
 // octaves so get short chunks whatever the cap: more work-groups, shorter
 // row loops.
 constexpr int kBlurTargetGroups = 2048;
+// Levels per blur launch when blur_chain is 0.
+constexpr int kDefaultChain = 2;
 
 int blur_class(int tile_rows, const int64_t* tiles_of_class) {
   int top = kNumTileH - 1;
@@ -146,6 +148,8 @@ sift_status validate_params(const sift_params& p) {
     return fail(SIFT_ERR_INVALID_ARG, "upsample_max_pixels must be >= 0");
   if (p.pyramid_fp16 != 0 && p.pyramid_fp16 != 1)
     return fail(SIFT_ERR_INVALID_ARG, "pyramid_fp16 must be 0 or 1");
+  if (p.blur_chain < 0 || p.blur_chain > kChainMaxLevels)
+    return fail(SIFT_ERR_INVALID_ARG, "blur_chain must be in 0..%d", kChainMaxLevels);
   // Window sizes.  A refined keypoint has layer + offset below s + 1/2, so
   // its octave scale stays below sigma0 * 2^((s + 1/2) / s).  The descriptor
   // scans a square of half-side ceil(2.5 * cell * (|cos| + |sin|)) + 1 for
@@ -552,49 +556,99 @@ sift_status launch_stages(const sift_handle* h, const Config& cfg, int32_t n, co
   const DevParams& p = cfg.dev;
   for (int64_t t : plan.tiles)
     if (t > INT32_MAX - kXcds) return fail(SIFT_ERR_TOO_LARGE, "batch has too many tiles");
-  if (plan.bands > INT32_MAX) return fail(SIFT_ERR_TOO_LARGE, "batch has too many bands");
+  if (plan.bands > INT32_MAX - kXcds) return fail(SIFT_ERR_TOO_LARGE, "batch has too many bands");
   int prec = prof_begin(kStSetup, 0.0, stream);
   if ((st = check_hip(launch_finalize(hp, n, p, stream), "finalize")) != SIFT_OK) return st;
   prof_end(prec, stream);
 
-  // scale space: one launch per (octave, level) over every image of the batch
+  // scale space: per octave, runs of consecutive levels in one launch each
+  // (k_chain) where a kernel for the run is built, else one launch per level
+  // (k_blur); both compute every value identically
+  const int max_chain = h->params.blur_chain == 0 ? kDefaultChain : h->params.blur_chain;
+  const LayoutCfg lc = layout_cfg(p);
   for (int k = 0; k < p.n_oct; ++k) {
-    for (int lv = (k == 0 ? 0 : 1); lv <= p.s + 2; ++lv) {
-      BlurArgs a;
-      std::memset(&a, 0, sizeof a);
-      const Taps& t = lv == 0 ? cfg.init : cfg.inc[lv - 1];
-      const int cls = blur_class(h->params.tile_rows, &plan.tiles[k * kNumTileH]);
-      const int th = tile_h_of(cls);
-      a.ws = ws;
-      a.table = hp.table;
-      a.tile_prefix = hp.tile_prefix + (int64_t)(cls * kMaxOct + k) * (n + 1);
-      a.n = n;
-      a.k = k;
-      a.dst_level = lv;
-      a.th = th;
-      a.p = p;
-      if (lv == 0) a.mode = p.upsample ? kSrcUpsample : kSrcImage;
-      else if (lv == 1 && k > 0) a.mode = kSrcDown;
-      else a.mode = kSrcLevel;
-      // storage of the level written and of its source level
-      const LayoutCfg lc = layout_cfg(p);
-      const int es_d = level_es(lc, k);
-      const int es_s = lv == 0 ? 4 : level_es(lc, a.mode == kSrcDown ? k - 1 : k);
-      a.st = es_d == 4 ? 0 : (es_s == 4 ? 1 : 2);
-      std::memcpy(a.taps, t.g, sizeof(float) * (2 * t.radius + 1));
+    const int cls = blur_class(h->params.tile_rows, &plan.tiles[k * kNumTileH]);
+    const int th = tile_h_of(cls);
+    const int grid = (int)((plan.tiles[k * kNumTileH + cls] + kXcds - 1) / kXcds * kXcds);
+    const int* tile_prefix = hp.tile_prefix + (int64_t)(cls * kMaxOct + k) * (n + 1);
+    const int es_d = level_es(lc, k);
+    for (int lv = (k == 0 ? 0 : 1); lv <= p.s + 2;) {
+      auto taps_of = [&](int level) -> const Taps& { return level == 0 ? cfg.init : cfg.inc[level - 1]; };
+      int mode;
+      if (lv == 0) mode = p.upsample ? kSrcUpsample : kSrcImage;
+      else if (lv == 1 && k > 0) mode = kSrcDown;
+      else mode = kSrcLevel;
+      // storage of the levels written and of their source
+      const int es_s = lv == 0 ? 4 : level_es(lc, mode == kSrcDown ? k - 1 : k);
+      const int st_mode = es_d == 4 ? 0 : (es_s == 4 ? 1 : 2);
+      int nl = 1;
+      int radii[kChainMaxLevels] = {};
+      for (int m = std::min(max_chain, p.s + 3 - lv); m >= 2; --m) {
+        for (int i = 0; i < m; ++i) radii[i] = taps_of(lv + i).radius;
+        if (chain_supported(mode, st_mode, m, radii)) {
+          nl = m;
+          break;
+        }
+      }
       // algorithmic bytes: the source read once (input pixels for the first
-      // level), the level written once, plus level 0 written when subsampling
-      double bytes = (double)(es_s + es_d) * plan.pixels[k];
-      if (lv == 0 && p.upsample) bytes = 4.0 * plan.pixels[k] + 4.0 * plan.input_px;
-      if (a.mode == kSrcDown) bytes += (double)es_d * plan.pixels[k];
+      // level), each level written once, plus level 0 written when subsampling
+      double bytes = (double)es_s * plan.pixels[k] + (double)nl * es_d * plan.pixels[k];
+      if (lv == 0 && p.upsample) bytes = 4.0 * plan.input_px + 4.0 * nl * plan.pixels[k];
+      if (mode == kSrcDown) bytes += (double)es_d * plan.pixels[k];
+      // a vertical and a horizontal pass of 2R + 1 taps per output pixel and level
+      double fmas = 0.0;
+      for (int i = 0; i < nl; ++i) fmas += 2.0 * (2 * taps_of(lv + i).radius + 1) * plan.pixels[k];
       char label[32];
-      std::snprintf(label, sizeof label, "o%d l%d R%d", k + p.o0, lv, t.radius);
-      // a vertical and a horizontal pass of 2R + 1 taps per output pixel
-      prec = prof_begin(kStBlur, bytes, stream, label, 2.0 * (2 * t.radius + 1) * plan.pixels[k]);
-      const int grid = (int)((plan.tiles[k * kNumTileH + cls] + kXcds - 1) / kXcds * kXcds);
-      if (grid > 0 && (st = check_hip(launch_blur(a, t.radius, grid, stream), "blur")) != SIFT_OK)
-        return st;
+      if (nl == 1)
+        std::snprintf(label, sizeof label, "o%d l%d R%d", k + p.o0, lv, taps_of(lv).radius);
+      else if (nl == 2)
+        std::snprintf(label, sizeof label, "o%d l%d-%d R%d,%d", k + p.o0, lv, lv + 1, radii[0],
+                      radii[1]);
+      else if (nl == 3)
+        std::snprintf(label, sizeof label, "o%d l%d-%d R%d,%d,%d", k + p.o0, lv, lv + 2, radii[0],
+                      radii[1], radii[2]);
+      else
+        std::snprintf(label, sizeof label, "o%d l%d-%d R%d,%d,%d,%d", k + p.o0, lv, lv + 3,
+                      radii[0], radii[1], radii[2], radii[3]);
+      prec = prof_begin(kStBlur, bytes, stream, label, fmas);
+      if (nl == 1) {
+        BlurArgs a;
+        std::memset(&a, 0, sizeof a);
+        const Taps& t = taps_of(lv);
+        a.ws = ws;
+        a.table = hp.table;
+        a.tile_prefix = tile_prefix;
+        a.n = n;
+        a.k = k;
+        a.dst_level = lv;
+        a.mode = mode;
+        a.th = th;
+        a.st = st_mode;
+        a.p = p;
+        std::memcpy(a.taps, t.g, sizeof(float) * (2 * t.radius + 1));
+        if (grid > 0 && (st = check_hip(launch_blur(a, t.radius, grid, stream), "blur")) != SIFT_OK)
+          return st;
+      } else {
+        ChainArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.ws = ws;
+        a.table = hp.table;
+        a.tile_prefix = tile_prefix;
+        a.n = n;
+        a.k = k;
+        a.lv0 = lv;
+        a.th = th;
+        a.p = p;
+        for (int i = 0; i < nl; ++i) {
+          const Taps& t = taps_of(lv + i);
+          for (int q = 0; q <= t.radius; ++q) a.g[i][q] = t.g[t.radius + q];
+        }
+        if (grid > 0 && (st = check_hip(launch_chain(a, mode, st_mode, nl, radii, grid, stream),
+                                        "blur chain")) != SIFT_OK)
+          return st;
+      }
       prof_end(prec, stream);
+      lv += nl;
     }
   }
   // detection and ordered compaction

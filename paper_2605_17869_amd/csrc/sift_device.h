@@ -178,6 +178,16 @@ __device__ __forceinline__ void store_at(gchar* row, uint32_t byte_off, float v)
   *reinterpret_cast<gfloat*>(row + byte_off) = v;
 }
 typedef __attribute__((address_space(1))) _Float16 ghalf;
+// fp16 of an fp32 value, nearest even.  The empty register constraint keeps
+// the compiler from folding the conversion into the instruction that made x
+// (a mixed-precision fma rounds the exact product-sum to fp16 once, which
+// differs from rounding the fp32 result at fp16 ties).
+__device__ __forceinline__ _Float16 f16_rn(float x) {
+  __asm__("" : "+v"(x));
+  return (_Float16)x;
+}
+// x rounded to fp16 and back
+__device__ __forceinline__ float round_f16(float x) { return (float)f16_rn(x); }
 // fp32 or fp16 (H16) element at a byte offset; stores round to nearest even
 template <bool H16>
 __device__ __forceinline__ float load_lv(const gchar* row, uint32_t byte_off) {
@@ -186,8 +196,34 @@ __device__ __forceinline__ float load_lv(const gchar* row, uint32_t byte_off) {
 }
 template <bool H16>
 __device__ __forceinline__ void store_lv(gchar* row, uint32_t byte_off, float v) {
-  if (H16) *reinterpret_cast<ghalf*>(row + byte_off) = (_Float16)v;
+  if (H16) *reinterpret_cast<ghalf*>(row + byte_off) = f16_rn(v);
   else *reinterpret_cast<gfloat*>(row + byte_off) = v;
+}
+// Four consecutive elements at a byte offset aligned to their total size (16
+// bytes fp32, 8 bytes fp16): one wide store.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <bool H16>
+__device__ __forceinline__ void store4_lv(gchar* row, uint32_t byte_off, const float* v) {
+  if (H16) {
+    typedef __attribute__((address_space(1))) u32x2 gu32x2;
+    const uint32_t lo = (uint32_t)__builtin_bit_cast(uint16_t, f16_rn(v[0])) |
+                        ((uint32_t)__builtin_bit_cast(uint16_t, f16_rn(v[1])) << 16);
+    const uint32_t hi = (uint32_t)__builtin_bit_cast(uint16_t, f16_rn(v[2])) |
+                        ((uint32_t)__builtin_bit_cast(uint16_t, f16_rn(v[3])) << 16);
+    u32x2 q;
+    q.x = lo;
+    q.y = hi;
+    *reinterpret_cast<gu32x2*>(row + byte_off) = q;
+  } else {
+    typedef __attribute__((address_space(1))) f32x4 gf32x4;
+    f32x4 q;
+    q.x = v[0];
+    q.y = v[1];
+    q.z = v[2];
+    q.w = v[3];
+    *reinterpret_cast<gf32x4*>(row + byte_off) = q;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -289,4 +289,22 @@ struct BlurArgs {
   float taps[2 * kMaxRadius + 1];
 };
 
+// Chained levels (k_chain): rows per step, most levels per launch, largest
+// radius (2R <= kChainB: a block of outputs needs two blocks of input rows).
+constexpr int kChainB = 16;
+constexpr int kChainMaxLevels = 4;
+constexpr int kChainMaxR = 8;
+
+struct ChainArgs {
+  char* ws;
+  const ImgEntry* table;
+  const int* tile_prefix;   // tiles of this octave and chunk height: n + 1 entries
+  int n;
+  int k;            // octave slot
+  int lv0;          // first level written
+  int th;           // chunk height
+  DevParams p;
+  float g[kChainMaxLevels][kChainMaxR + 1];   // g[i][t]: tap at distance t of level lv0 + i
+};
+
 }  // namespace sift

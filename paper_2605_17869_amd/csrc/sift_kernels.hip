@@ -148,7 +148,10 @@ __global__ __launch_bounds__(kDetectWaves * 64) void k_detect(char* ws, HdrPtrs 
                                                              DevParams p) {
   __shared__ int s_cnt[kDetectWaves][S];
   const int* bp = hp.band_prefix;
-  const int item = blockIdx.x;
+  // bands dealt to the XCDs in contiguous runs (the grid is a multiple of 8):
+  // a band's halo rows are its neighbours' rows, read through the same L2
+  const int per_xcd = gridDim.x / kXcds;
+  const int item = (blockIdx.x % kXcds) * per_xcd + blockIdx.x / kXcds;
   if (item >= bp[n]) return;   // a grid sized for larger images than the table's
   const int img = find_owner(bp, n, item);
   const int lb = item - bp[img];
@@ -910,6 +913,7 @@ hipError_t launch_finalize(const HdrPtrs& hp, int n, const DevParams& p, hipStre
 
 hipError_t launch_detect(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
                          hipStream_t stream) {
+  grid = (grid + kXcds - 1) / kXcds * kXcds;
 #define SIFT_DETECT_CASE(SS)                                                              \
   case SS:                                                                                \
     return p.h16 ? launch(k_detect<SS, true>, dim3(grid), dim3(kDetectWaves * 64), stream, \

@@ -18,6 +18,12 @@ hipError_t launch_setup(const HdrPtrs& hp, const SetupChunk& c, hipStream_t stre
 hipError_t launch_finalize(const HdrPtrs& hp, int n, const DevParams& p, hipStream_t stream);
 // Gaussian level: `radius` selects the instantiation; taps in a.taps[0..2R].
 hipError_t launch_blur(const BlurArgs& a, int radius, int grid, hipStream_t stream);
+// Chained levels lv0 .. lv0 + n_levels - 1 of one octave from the source that
+// `mode` names; st as for BlurArgs.  chain_supported tells whether a kernel
+// for that (mode, st, radii) run is built.
+bool chain_supported(int mode, int st, int n_levels, const int* radii);
+hipError_t launch_chain(const ChainArgs& a, int mode, int st, int n_levels, const int* radii,
+                        int grid, hipStream_t stream);
 hipError_t launch_detect(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
                          hipStream_t stream);
 hipError_t launch_band_scan(char* ws, const HdrPtrs& hp, int n, const DevParams& p,

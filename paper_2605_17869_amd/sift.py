@@ -40,7 +40,7 @@ class SiftParams(ctypes.Structure):
         ("rootsift", ctypes.c_int32), ("max_keypoints", ctypes.c_int32),
         ("max_candidates", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
         ("n_streams", ctypes.c_int32), ("upsample_max_pixels", ctypes.c_int32),
-        ("pyramid_fp16", ctypes.c_int32),
+        ("pyramid_fp16", ctypes.c_int32), ("blur_chain", ctypes.c_int32),
     ]
 
 

@@ -86,12 +86,15 @@ def test_defaults_and_parameter_validation():
                       (dict(border=0), 1), (dict(desc_width=3), 6), (dict(upsample=2), 1),
                       (dict(n_octaves=12, upsample=1), 6), (dict(sigma0=9.0), 6),
                       (dict(max_candidates=0), 1), (dict(ori_peak_ratio=1.5), 1),
-                      (dict(tile_rows=48), 1), (dict(tile_rows=1024), 1), (dict(n_streams=9), 1)]:
+                      (dict(tile_rows=48), 1), (dict(tile_rows=1024), 1), (dict(n_streams=9), 1),
+                      (dict(blur_chain=-1), 1), (dict(blur_chain=5), 1)]:
         pp = S.make_params(**bad)
         assert lib.sift_create(ctypes.byref(pp), ctypes.byref(h)) == code, bad
         assert lib.sift_last_error()
     for rows in (0, 32, 64, 128, 256, 512):
         S.Extractor(tile_rows=rows)
+    for chain in range(5):
+        S.Extractor(blur_chain=chain)
     with pytest.raises(S.SiftError):
         S.Extractor(n_scales=0)
     ex = S.Extractor(dsp_scales=[0.5, 1.0, 2.0], rootsift=1)
