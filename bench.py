@@ -30,10 +30,10 @@ from paper_2605_17869_amd import synth  # noqa: E402
 from paper_2605_17869_amd.build import kernel_source_hash  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# HBM traffic of the blur kernel measured with rocprofv3 counters (summary text)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_blur_hbm_traffic_w2.txt")
+# HBM traffic of the pyramid kernels measured with rocprofv3 counters (summary text)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pyramid_hbm_traffic_w2.txt")
 def measured_traffic():
-    """HBM bytes per blur launch from the committed counter summary, or None
+    """HBM bytes per pyramid launch from the committed counter summary, or None
     when it is missing or was taken on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
@@ -373,6 +373,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0,
                     help="blur chunk height (0: autotuned on the batch unless --no-autotune)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--blur-chain", type=int, default=0,
+                    help="pyramid levels per launch (0: autotuned unless --no-autotune, else 2)")
     ap.add_argument("--n-streams", type=int, default=0,
                     help="sub-batches of a batched call (0: library choice, 1: one launch sequence)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
@@ -428,18 +430,21 @@ def main():
     sizes = [tuple(im.shape) for im in imgs]
     stream = torch.cuda.current_stream()
     tune = None
-    tile_rows, n_streams = args.tile_rows, args.n_streams
+    tile_rows, n_streams, blur_chain = args.tile_rows, args.n_streams, args.blur_chain
     if tile_rows == 0 and not args.no_autotune:
-        # both launch knobs (chunk-height cap x sub-batch count), timed afresh
-        # in the form the line reports (graph replay, unless --no-graph)
-        probe = sm.Extractor(wl.settings)
+        # the launch knobs (chunk-height cap x sub-batch count, then pyramid
+        # levels per launch), timed afresh in the form the line reports (graph
+        # replay, unless --no-graph)
+        probe = sm.Extractor(dict(wl.settings, blur_chain=blur_chain))
         tune = probe.tune(d_imgs, warmup=1, reps=5, as_graph=not args.no_graph, stream=stream)
         tile_rows = tune["tile_rows"]
         if n_streams == 0:
             n_streams = tune["n_streams"]
+        if blur_chain == 0:
+            blur_chain = tune["blur_chain"]
         del probe
         print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
-    settings = dict(wl.settings, tile_rows=tile_rows, n_streams=n_streams)
+    settings = dict(wl.settings, tile_rows=tile_rows, n_streams=n_streams, blur_chain=blur_chain)
     ex = sm.Extractor(settings)
     ws = torch.empty(ex.batch_workspace_size(sizes), dtype=torch.uint8, device=dev)
     outs = [ex.alloc_features() for _ in range(n)]
@@ -551,7 +556,8 @@ def main():
         if blur:
             launches, bms, bbytes = blur
             achieved = (bbytes / launches) / (bms / launches * 1e-3) / 1e9
-            roofline = {"kernel": "k_blur (separable Gaussian level, all radii)", "bound": "hbm",
+            roofline = {"kernel": "Gaussian pyramid: k_chain (runs of levels, radius <= 8) and "
+                                  "k_blur (single levels)", "bound": "hbm",
                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                         "avg_launch_us": round(1e3 * bms / launches, 2),
@@ -645,7 +651,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "images": n, "image_size": (f"{sizes[0][1]}x{sizes[0][0]}" if len(set(sizes)) == 1
                                   else f"mixed, mean {mpix / n:.3f} Mpix"),
-                   "tile_rows": tile_rows, "n_streams": n_streams,
+                   "tile_rows": tile_rows, "n_streams": n_streams, "blur_chain": blur_chain,
                    "upsample": wl.settings["upsample"], "octaves": wl.settings["n_octaves"] +
                    wl.settings["upsample"], "parallelism": "none (one GPU)"},
         "mpix_per_s": round(mpix / (ms * 1e-3), 2),

@@ -333,20 +333,22 @@ sift_status sift_autotune_batch(const sift_params* p, int32_t n, const float* co
                                 float* ms);
 
 /*
- * Tuning over both launch knobs, with a persisted cache.  sift_autotune
+ * Tuning over the launch knobs, with a persisted cache.  sift_autotune
  * times sift_extract_batch on the given batch for every blur chunk-height cap
- * (64, 128, 256, 512) and every sub-batch count (1, 2, 4, 8, at most n) --
- * all of them give bit-identical results -- and returns the fastest pair in
- * *out.  With cache_path non-NULL it first looks the batch up in that text
- * file (one line per entry: key, tile_rows, n_streams, ms; the last entry of
- * a key wins) and, on a hit, returns the entry without timing (from_cache =
- * 1); after timing it appends the winner.  The key names the device (name,
- * architecture, compute units), the settings other than the two tuned fields,
- * the image count, the total input pixels to two significant figures and the
- * execution form: as_graph = 0 times the launch sequence (sift_extract_batch),
- * 1 times replays of it recorded as a graph (sift_graph_*), whose best split
- * can differ.  It synchronises on `stream` when it times; not for a capture
- * or a hot loop.
+ * (64, 128, 256, 512) and every sub-batch count (1, 2, 4, 8, at most n) at
+ * the settings' blur_chain, then the other pyramid run lengths (1, 2, 3
+ * levels per launch) at the best of those -- all of them give bit-identical
+ * results -- and returns the fastest in *out.  With cache_path non-NULL it
+ * first looks the batch up in that text file (one line per entry: key,
+ * tile_rows, n_streams, blur_chain, ms; the last entry of a key wins) and, on
+ * a hit, returns the entry without timing (from_cache = 1); after timing it
+ * appends the winner.  The key names the device (name, architecture, compute
+ * units), the settings other than the three tuned fields, the image count,
+ * the total input pixels to two significant figures and the execution form:
+ * as_graph = 0 times the launch sequence (sift_extract_batch), 1 times
+ * replays of it recorded as a graph (sift_graph_*), whose best split can
+ * differ.  It synchronises on `stream` when it times; not for a capture or a
+ * hot loop.
  */
 typedef struct {
   int32_t tile_rows;    /* chosen chunk-height cap */
@@ -354,6 +356,7 @@ typedef struct {
   float ms;             /* its mean time per batch, ms */
   int32_t from_cache;   /* 1: read from the cache file, nothing timed */
   int32_t n_tried;      /* candidates timed */
+  int32_t blur_chain;   /* chosen pyramid levels per launch (1..3) */
 } sift_tuning;
 
 /* Workspace that every candidate of sift_autotune fits in (a split into more

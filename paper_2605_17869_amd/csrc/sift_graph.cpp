@@ -184,6 +184,7 @@ std::string tune_key(const sift_params* p, int32_t n, const int32_t* heights, co
   sift_params q = *p;
   q.tile_rows = 0;
   q.n_streams = 0;
+  q.blur_chain = 0;
   double px = 0.0;
   for (int i = 0; i < n; ++i) px += (double)heights[i] * widths[i];
   const double mag = px > 0 ? std::pow(10.0, std::floor(std::log10(px)) - 1.0) : 1.0;
@@ -210,7 +211,7 @@ bool cache_lookup(const char* path, const std::string& key, sift_tuning* t) {
     std::string k;
     sift_tuning v;
     std::memset(&v, 0, sizeof v);
-    if (is >> k >> v.tile_rows >> v.n_streams >> v.ms && k == key) {
+    if (is >> k >> v.tile_rows >> v.n_streams >> v.blur_chain >> v.ms && k == key) {
       *t = v;
       found = true;
     }
@@ -264,7 +265,8 @@ sift_status sift_autotune(const sift_params* p, int32_t n, const float* const* d
     return SIFT_ERR_INVALID_ARG;
   }
   std::memset(out, 0, sizeof *out);
-  const std::string key = tune_key(p, n, heights, widths) + (as_graph ? "/graph" : "/eager");
+  const std::string key =
+      tune_key(p, n, heights, widths) + (as_graph ? "/graph" : "/eager") + "/v2";
   if (cache_lookup(cache_path, key, out)) {
     out->from_cache = 1;
     return SIFT_OK;
@@ -281,65 +283,79 @@ sift_status sift_autotune(const sift_params* p, int32_t n, const float* const* d
   const int32_t streams[4] = {1, 2, 4, 8};
   sift_status st = SIFT_OK;
   float best = -1.0f;
-  for (int c = 0; c < 4 && st == SIFT_OK; ++c) {
-    for (int q = 0; q < 4 && st == SIFT_OK; ++q) {
-      if (streams[q] > n) continue;
-      sift_params pp = *p;
-      pp.tile_rows = rows[c];
-      pp.n_streams = streams[q];
-      sift_handle* h = nullptr;
-      st = sift_create(&pp, &h);
-      if (st != SIFT_OK) break;
-      size_t need = 0;
-      st = sift_batch_workspace_size(h, n, heights, widths, &need);
-      if (st == SIFT_OK && need > workspace_bytes) {   // a split the workspace cannot hold
-        sift_destroy(h);
-        continue;
-      }
-      // one extraction of the batch: the launch sequence, or a replay of it
-      // recorded as a graph
-      sift_graph* gr = nullptr;
-      if (st == SIFT_OK && as_graph)
-        st = sift_graph_create(h, n, d_images, heights, widths, pitches, d_workspace,
-                               workspace_bytes, outs, &gr);
-      auto once = [&]() {
-        return gr ? sift_graph_launch(gr, stream)
-                  : sift_extract_batch(h, n, d_images, heights, widths, pitches, d_workspace,
-                                       workspace_bytes, outs, stream);
-      };
-      for (int i = 0; i < warmup && st == SIFT_OK; ++i) st = once();
-      if (st == SIFT_OK && (e = hipEventRecord(a, stream)) != hipSuccess)
-        st = hip_fail(e, "autotune event");
-      for (int i = 0; i < reps && st == SIFT_OK; ++i) st = once();
-      float t = 0.0f;
-      if (st == SIFT_OK && (e = hipEventRecord(b, stream)) != hipSuccess)
-        st = hip_fail(e, "autotune event");
-      if (st == SIFT_OK && (e = hipEventSynchronize(b)) != hipSuccess)
-        st = hip_fail(e, "autotune wait");
-      if (st == SIFT_OK && (e = hipEventElapsedTime(&t, a, b)) != hipSuccess)
-        st = hip_fail(e, "autotune timing");
-      if (gr) {
-        if (st == SIFT_OK) st = sift_graph_destroy(gr);
-        else sift_graph_destroy(gr);
-      }
+  // times one candidate; a split the workspace cannot hold is skipped
+  auto try_one = [&](int32_t tile_rows, int32_t n_streams, int32_t chain) {
+    sift_params pp = *p;
+    pp.tile_rows = tile_rows;
+    pp.n_streams = n_streams;
+    pp.blur_chain = chain;
+    sift_handle* h = nullptr;
+    st = sift_create(&pp, &h);
+    if (st != SIFT_OK) return;
+    size_t need = 0;
+    st = sift_batch_workspace_size(h, n, heights, widths, &need);
+    if (st == SIFT_OK && need > workspace_bytes) {
       sift_destroy(h);
-      if (st != SIFT_OK) break;
-      t /= (float)reps;
-      out->n_tried += 1;
-      if (best < 0.0f || t < best) {
-        best = t;
-        out->tile_rows = rows[c];
-        out->n_streams = streams[q];
-        out->ms = t;
-      }
+      return;
     }
+    // one extraction of the batch: the launch sequence, or a replay of it
+    // recorded as a graph
+    sift_graph* gr = nullptr;
+    if (st == SIFT_OK && as_graph)
+      st = sift_graph_create(h, n, d_images, heights, widths, pitches, d_workspace,
+                             workspace_bytes, outs, &gr);
+    auto once = [&]() {
+      return gr ? sift_graph_launch(gr, stream)
+                : sift_extract_batch(h, n, d_images, heights, widths, pitches, d_workspace,
+                                     workspace_bytes, outs, stream);
+    };
+    for (int i = 0; i < warmup && st == SIFT_OK; ++i) st = once();
+    if (st == SIFT_OK && (e = hipEventRecord(a, stream)) != hipSuccess)
+      st = hip_fail(e, "autotune event");
+    for (int i = 0; i < reps && st == SIFT_OK; ++i) st = once();
+    float t = 0.0f;
+    if (st == SIFT_OK && (e = hipEventRecord(b, stream)) != hipSuccess)
+      st = hip_fail(e, "autotune event");
+    if (st == SIFT_OK && (e = hipEventSynchronize(b)) != hipSuccess)
+      st = hip_fail(e, "autotune wait");
+    if (st == SIFT_OK && (e = hipEventElapsedTime(&t, a, b)) != hipSuccess)
+      st = hip_fail(e, "autotune timing");
+    if (gr) {
+      if (st == SIFT_OK) st = sift_graph_destroy(gr);
+      else sift_graph_destroy(gr);
+    }
+    sift_destroy(h);
+    if (st != SIFT_OK) return;
+    t /= (float)reps;
+    out->n_tried += 1;
+    if (best < 0.0f || t < best) {
+      best = t;
+      out->tile_rows = tile_rows;
+      out->n_streams = n_streams;
+      out->blur_chain = chain;
+      out->ms = t;
+    }
+  };
+  // chunk height x sub-batch count at the caller's chain setting, then the
+  // other chain lengths at the best of those (the pyramid's levels per launch
+  // barely interact with the split)
+  const int32_t chain0 = p->blur_chain == 0 ? 2 : p->blur_chain;
+  for (int c = 0; c < 4 && st == SIFT_OK; ++c)
+    for (int q = 0; q < 4 && st == SIFT_OK; ++q)
+      if (streams[q] <= n) try_one(rows[c], streams[q], chain0);
+  if (st == SIFT_OK && best >= 0.0f) {
+    const int32_t r0 = out->tile_rows, s0 = out->n_streams;
+    for (int32_t chain = 1; chain <= 3 && st == SIFT_OK; ++chain)
+      if (chain != chain0) try_one(r0, s0, chain);
   }
   hipEventDestroy(a);
   hipEventDestroy(b);
   if (st != SIFT_OK) return st;
   if (cache_path) {
     std::ofstream f(cache_path, std::ios::app);
-    if (f) f << key << " " << out->tile_rows << " " << out->n_streams << " " << out->ms << "\n";
+    if (f)
+      f << key << " " << out->tile_rows << " " << out->n_streams << " " << out->blur_chain << " "
+        << out->ms << "\n";
   }
   return SIFT_OK;
 }

@@ -101,7 +101,8 @@ def main(argv=None):
             name = next(k for k in cv if cal_kernel in k)
             cn, cs = cv[name]
             scale = cal_bytes / (cs / cn * 1024.0)
-            kv = [(n, s_) for k, (n, s_) in counter_values(db, counter).items() if k.startswith(prefix)]
+            prefixes = tuple(prefix.split(","))
+            kv = [(n, s_) for k, (n, s_) in counter_values(db, counter).items() if k.startswith(prefixes)]
             launches = sum(n for n, _ in kv)
             raw = sum(s_ for _, s_ in kv) / launches * 1024.0
             out[counter] = raw * scale

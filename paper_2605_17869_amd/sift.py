@@ -96,7 +96,8 @@ MATCH_DTYPE = np.dtype([("query", "<i4"), ("train", "<i4"), ("similarity", "<f4"
 
 class SiftTuning(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("n_streams", ctypes.c_int32),
-                ("ms", ctypes.c_float), ("from_cache", ctypes.c_int32), ("n_tried", ctypes.c_int32)]
+                ("ms", ctypes.c_float), ("from_cache", ctypes.c_int32), ("n_tried", ctypes.c_int32),
+                ("blur_chain", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -481,7 +482,7 @@ class Extractor:
 
     def tune(self, images, warmup: int = 1, reps: int = 3, cache_path: str | None = None,
              as_graph: bool = False, outs=None, workspace=None, stream=None) -> dict:
-        """``sift_autotune``: the fastest (tile_rows, n_streams) for this batch
+        """``sift_autotune``: the fastest (tile_rows, n_streams, blur_chain) for this batch
         run as a launch sequence (or, ``as_graph``, as graph replays), from
         ``cache_path`` when it holds the batch's key."""
         import torch
@@ -500,7 +501,8 @@ class Extractor:
         _check(self.lib.sift_autotune(ctypes.byref(self.params), *args, _stream_handle(stream),
                                       warmup, reps, 1 if as_graph else 0, path, ctypes.byref(t)),
                "sift_autotune")
-        return {"tile_rows": t.tile_rows, "n_streams": t.n_streams, "ms": round(t.ms, 4),
+        return {"tile_rows": t.tile_rows, "n_streams": t.n_streams, "blur_chain": t.blur_chain,
+                "ms": round(t.ms, 4),
                 "from_cache": bool(t.from_cache), "candidates_timed": t.n_tried,
                 "timed_as": "graph replay" if as_graph else "launch sequence"}
 

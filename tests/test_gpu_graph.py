@@ -109,7 +109,7 @@ def test_bucket_needs_one_octave_structure():
 
 
 def test_tuning_cache_round_trip(tmp_path):
-    """sift_autotune times both knobs, appends the winner to the cache file,
+    """sift_autotune times the launch knobs, appends the winner to the cache file,
     and a second call with the same batch reads it back without timing; the
     tuned handle gives the same bits as any other setting."""
     torch = require_gpu()
@@ -122,13 +122,16 @@ def test_tuning_cache_round_trip(tmp_path):
     say(f"tuned: {first}")
     assert not first["from_cache"] and first["candidates_timed"] >= 4
     assert first["tile_rows"] in (64, 128, 256, 512) and first["n_streams"] in (1, 2)
+    assert first["blur_chain"] in (1, 2, 3)
     again = ex.tune(bufs, warmup=1, reps=1, cache_path=cache)
     assert again["from_cache"] and again["candidates_timed"] == 0
-    assert (again["tile_rows"], again["n_streams"]) == (first["tile_rows"], first["n_streams"])
+    knobs = lambda t: (t["tile_rows"], t["n_streams"], t["blur_chain"])
+    assert knobs(again) == knobs(first)
     graph = ex.tune(bufs, warmup=1, reps=1, cache_path=cache, as_graph=True)
     assert not graph["from_cache"] and graph["candidates_timed"] >= 4   # its own key
     assert ex.tune(bufs, warmup=1, reps=1, cache_path=cache, as_graph=True)["from_cache"]
-    tuned = Extractor(dict(SETTINGS, tile_rows=first["tile_rows"], n_streams=first["n_streams"]))
+    tuned = Extractor(dict(SETTINGS, tile_rows=first["tile_rows"], n_streams=first["n_streams"],
+                           blur_chain=first["blur_chain"]))
     ref = [extract(ex, im) for im in imgs]
     feats = tuned.extract_batch(bufs)
     torch.cuda.synchronize()
