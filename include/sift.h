@@ -148,11 +148,16 @@ typedef struct {
 
 typedef struct sift_handle sift_handle;
 
-/* Fill *p with the defaults listed above.  Errors: INVALID_ARG if p is NULL. */
+/* Fill *p with the defaults listed above (the settings section 3.2 states: 36
+ * orientation bins, 4x4x8 descriptor, at most 5 refinement steps, 4-sigma
+ * truncation; the rest as in Lowe's SIFT, which the paper follows).  Errors:
+ * INVALID_ARG if p is NULL. */
 sift_status sift_params_default(sift_params* p);
 
 /* Validate *p and create an immutable handle (host memory only; no device
- * allocation).  Errors: INVALID_ARG / NOT_SUPPORTED for bad or unimplemented
+ * allocation).  It derives the level blurs of section 3.2 "GPU Pipeline
+ * Stages" (sigma0 * 2^(i/s) per level, each level blurred incrementally from
+ * the previous one with a separable kernel truncated at 4 sigma).  Errors: INVALID_ARG / NOT_SUPPORTED for bad or unimplemented
  * settings.  The caller releases the handle with sift_destroy. */
 sift_status sift_create(const sift_params* p, sift_handle** out);
 void sift_destroy(sift_handle* h);
@@ -160,13 +165,20 @@ void sift_destroy(sift_handle* h);
 /* Copy the handle's settings into *p. */
 sift_status sift_get_params(const sift_handle* h, sift_params* p);
 
-/* Device workspace bytes sift_extract needs for a height x width image.
- * Errors: INVALID_ARG, IMAGE_TOO_SMALL, TOO_LARGE. */
+/* Device workspace bytes sift_extract needs for a height x width image: the
+ * pyramid of section 3.2 (s + 3 levels per octave) plus detection and
+ * keypoint state.  Errors: INVALID_ARG, IMAGE_TOO_SMALL, TOO_LARGE. */
 sift_status sift_workspace_size(const sift_handle* h, int32_t height, int32_t width,
                                 size_t* bytes);
 
-/* Extract one image: d_image is a device float32 array of height rows of
- * `pitch` elements (pitch >= width), values nominally in [0, 1].
+/* Extract one image, the whole extraction of Eq. (1) as section 3.2 "GPU
+ * Pipeline Stages" lays it out (scale space, DoG, extrema with the contrast
+ * pre-gate, refinement and edge rejection, orientation, descriptor with the
+ * "DSP Multi-Scale Descriptor Pooling" and "RootSIFT Normalization"
+ * paragraphs), on the GPU from input to descriptors (the device-resident
+ * pipeline of section 3.1, "Architecture Overview").  d_image is a device float32 array
+ * of height rows of `pitch` elements (pitch >= width), values nominally in
+ * [0, 1].
  * d_workspace (device, >= sift_workspace_size bytes, 256-byte aligned) holds
  * the pyramid and all intermediate state; its contents on entry do not
  * matter.  Results land in *out (see sift_output). */
@@ -206,7 +218,9 @@ sift_status sift_batch_workspace_size(const sift_handle* h, int32_t n, const int
 
 /* Extract n images of possibly different sizes in one launch sequence:
  * every stage runs once for the whole batch over (image, octave, tile) work
- * items.  d_images, heights, widths, pitches and outs are host arrays of n
+ * items.  The paper runs its ~20 kernels once per image and names that launch
+ * count as its throughput ceiling (section 5, "Throughput Ceiling vs. Learned
+ * Detectors"); the per-image computation is that of sift_extract.  d_images, heights, widths, pitches and outs are host arrays of n
  * entries (d_images[k] is a device pointer).  Each image's results are
  * bit-identical to sift_extract on that image alone. */
 sift_status sift_extract_batch(sift_handle* h, int32_t n, const float* const* d_images,
