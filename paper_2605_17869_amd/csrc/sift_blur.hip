@@ -423,6 +423,15 @@ __global__ __launch_bounds__(kBlurThreads, 2) void k_chain(ChainArgs a) {
     constexpr int NREP = (B * NQ + NT - 1) / NT;
     constexpr int SH = R & 3;                   // s_v offset: aligned task reads
     constexpr int NH = (2 * R + 4 + 3) / 4;     // float4 reads per task
+    // every LDS access stays in its row and the columns each level reads were
+    // produced by the level before it (or fetched, for the first)
+    static_assert((HS - HL - R + SH) >= 0 && (HS - HL - R + SH) % 4 == 0, "aligned task reads");
+    static_assert(HS - HL - R + SH + 4 * (NQ - 1) + 4 * NH <= SS, "task reads inside a row");
+    static_assert(NT - 1 + SH < SS, "vertical-pass writes inside a row");
+    static_assert((HS - HL) % 4 == 0 && HS - HL + 4 * NQ <= SS, "handed-over rows inside a row");
+    static_assert(HS + TW + HL + R <= NT, "input columns are threads' columns");
+    static_assert(I == 0 || Geo::hl(I == 0 ? 0 : I - 1) >= HL + R, "input columns were produced");
+    static_assert(Q >= 2 * Geo::lag(I) + I * B, "first valid row at or above y0 - Lag");
     const int ai = y0 - Q + Geo::lag(I) + g * B;   // A_I(g)
     if constexpr (I > 0) {
       if (g < I - 1) return;   // level I - 1 produced nothing valid yet
