@@ -35,14 +35,14 @@ __device__ __forceinline__ bool top2_better(float va, int ia, float vb, int ib) 
   return va > vb || (va == vb && ia < ib);
 }
 
-__device__ __forceinline__ void top2_push(Top2& t, float v, int i) {
-  if (top2_better(v, i, t.v1, t.i1)) {
-    t.v2 = fmaxf(t.v2, t.v1);
-    t.v1 = v;
-    t.i1 = i;
-  } else {
-    t.v2 = fmaxf(t.v2, v);
-  }
+// Add (v, i) to t, for an index larger than every index pushed into t
+// before: a tie then keeps the earlier entry, so "better" is a strict
+// comparison of values, and a displaced first value is never below the second.
+__device__ __forceinline__ void top2_push_after(Top2& t, float v, int i) {
+  const bool up = v > t.v1;
+  t.v2 = up ? t.v1 : fmaxf(t.v2, v);
+  t.i1 = up ? i : t.i1;
+  t.v1 = up ? v : t.v1;
 }
 
 __device__ __forceinline__ Top2 top2_merge(const Top2& a, const Top2& b) {
@@ -179,7 +179,8 @@ __global__ __launch_bounds__(256) void k_match_rows(MatchHdr h, int n) {
           acc[ta][tb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(fa[ta][kk], fb[tb], acc[ta][tb],
                                                                0, 0, 0);
     }
-    // rows: this lane's b row of each block
+    // rows: this lane's b row of each block (a lane's b rows come in
+    // increasing order, over tb and over tiles)
 #pragma unroll
     for (int tb = 0; tb < 4; ++tb) {
       const int jb = col0 + 64 * bhalf + 16 * tb + li;
@@ -187,10 +188,11 @@ __global__ __launch_bounds__(256) void k_match_rows(MatchHdr h, int n) {
 #pragma unroll
         for (int ta = 0; ta < 4; ++ta)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) top2_push(rs[ta][r], acc[ta][tb][r], jb);
+          for (int r = 0; r < 4; ++r) top2_push_after(rs[ta][r], acc[ta][tb][r], jb);
       }
     }
-    // columns: b row 16 tb + li over this wave's 64 a rows
+    // columns: b row 16 tb + li over this wave's 64 a rows (in increasing
+    // order over ta and r)
 #pragma unroll
     for (int tb = 0; tb < 4; ++tb) {
       Top2 c = top2_empty();
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(256) void k_match_rows(MatchHdr h, int n) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int ia = row0 + 64 * ahalf + 16 * ta + 4 * gq + r;
-          if (ia < na) top2_push(c, acc[ta][tb][r], ia);
+          if (ia < na) top2_push_after(c, acc[ta][tb][r], ia);
         }
       c = top2_merge(c, top2_shfl_xor(c, 16));
       c = top2_merge(c, top2_shfl_xor(c, 32));
