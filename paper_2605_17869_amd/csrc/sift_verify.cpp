@@ -59,7 +59,7 @@ Layout layout_of(int32_t n, const sift_verify_pair* pairs, int32_t n_hyp) {
     L.pts.push_back(off);
     off = align256(off + cap * 32);
     L.raw.push_back(off);
-    off = align256(off + cap * 32);
+    off = align256(off + cap * 16);
     L.norm.push_back(off);
     off = align256(off + 8 * 8);
     L.scores.push_back(off);

@@ -29,7 +29,7 @@ struct VerifyEntry {
   int32_t cap;
   int32_t pad;
   int64_t pts;       // double [cap][4]: normalised (xa, ya, xb, yb)
-  int64_t raw;       // double [cap][4]: pixel (xa, ya, xb, yb)
+  int64_t raw;       // float4 [cap]: pixel (xa, ya, xb, yb), the keypoints' fp32 values
   int64_t norm;      // double [8]: sa, txa, tya, sb, txb, tyb, n (as double), unused
   int64_t scores;    // double [n_hyp]
 };

@@ -137,16 +137,33 @@ __device__ __forceinline__ void dlt_rows(double x, double y, double u, double v,
   r2[6] = -v * x; r2[7] = -v * y; r2[8] = v;
 }
 
-// Residual of correspondence (ax, ay) -> (bx, by) under H; infinite when the
-// point maps to or behind the line at infinity.
-__device__ __forceinline__ double residual(const double* H, double ax, double ay, double bx,
-                                           double by) {
+// Weight of correspondence (ax, ay) -> (bx, by) under H: marginal_w of the
+// residual r = |(x / w - bx, y / w - by)|, (x, y, w) = H (ax, ay, 1); 0 when
+// w <= 0 (the point maps to or behind the line at infinity).  The cut
+// r < tau * smax is first tested without divisions, on
+// |(x, y) - (bx, by) w|^2 < (tau smax w)^2 relaxed by 1e-9 (far more than the
+// rounding that separates the two forms); only where that admits the
+// correspondence is r formed, and marginal_w's exact test and weight decide,
+// so the filter changes no result.
+__device__ __forceinline__ double weight_at(const double* H, double ax, double ay, double bx,
+                                            double by, double smax) {
   const double x = (ax * H[0] + ay * H[1]) + H[2];
   const double y = (ax * H[3] + ay * H[4]) + H[5];
   const double w = (ax * H[6] + ay * H[7]) + H[8];
-  if (!(w > 0.0)) return INFINITY;
+  if (!(w > 0.0)) return 0.0;
+  const double ex = x - bx * w, ey = y - by * w, lim = kTau * smax * w;
+  if (!(ex * ex + ey * ey < (lim * lim) * (1.0 + 1e-9))) return 0.0;
   const double dx = x / w - bx, dy = y / w - by;
-  return sqrt(dx * dx + dy * dy);
+  return marginal_w(sqrt(dx * dx + dy * dy), smax);
+}
+
+// Pixel positions of correspondence i (stored as the keypoints' fp32 values).
+struct RawPt {
+  double ax, ay, bx, by;
+};
+__device__ __forceinline__ RawPt raw_at(const float4* raw, int i) {
+  const float4 v = raw[i];
+  return RawPt{(double)v.x, (double)v.y, (double)v.z, (double)v.w};
 }
 
 // The model of minimal sample k (wave-level; A: 72 doubles of this wave's LDS).
@@ -190,19 +207,17 @@ __global__ __launch_bounds__(256) void k_verify_prep(VerifyHdr hd, int n_pairs) 
   __shared__ double s4[4];
   const VerifyEntry e = hd.table[blockIdx.x];
   const int n = verify_count(e);
-  double* raw = reinterpret_cast<double*>(hd.ws + e.raw);
+  float4* raw = reinterpret_cast<float4*>(hd.ws + e.raw);
   double* pts = reinterpret_cast<double*>(hd.ws + e.pts);
   double* nrm = reinterpret_cast<double*>(hd.ws + e.norm);
   double sx[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < n; i += 256) {
     const sift_match m = e.matches[i];
     const sift_keypoint ka = e.kp_a[m.query], kb = e.kp_b[m.train];
+    raw[i] = make_float4(ka.x, ka.y, kb.x, kb.y);
     const double v[4] = {(double)ka.x, (double)ka.y, (double)kb.x, (double)kb.y};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      raw[4 * (int64_t)i + q] = v[q];
-      sx[q] += v[q];
-    }
+    for (int q = 0; q < 4; ++q) sx[q] += v[q];
   }
   double c[4];
 #pragma unroll
@@ -210,8 +225,8 @@ __global__ __launch_bounds__(256) void k_verify_prep(VerifyHdr hd, int n_pairs) 
   __syncthreads();
   double da = 0.0, db = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
-    const double* p = raw + 4 * (int64_t)i;
-    const double xa = p[0] - c[0], ya = p[1] - c[1], xb = p[2] - c[2], yb = p[3] - c[3];
+    const RawPt q = raw_at(raw, i);
+    const double xa = q.ax - c[0], ya = q.ay - c[1], xb = q.bx - c[2], yb = q.by - c[3];
     da += sqrt(xa * xa + ya * ya);
     db += sqrt(xb * xb + yb * yb);
   }
@@ -221,12 +236,12 @@ __global__ __launch_bounds__(256) void k_verify_prep(VerifyHdr hd, int n_pairs) 
   const double t[6] = {sa, -sa * c[0], -sa * c[1], sb, -sb * c[2], -sb * c[3]};
   if (threadIdx.x < 6) nrm[threadIdx.x] = t[threadIdx.x];
   for (int i = threadIdx.x; i < n; i += 256) {
-    const double* p = raw + 4 * (int64_t)i;
+    const RawPt q = raw_at(raw, i);
     double* o = pts + 4 * (int64_t)i;
-    o[0] = sa * p[0] + t[1];
-    o[1] = sa * p[1] + t[2];
-    o[2] = sb * p[2] + t[4];
-    o[3] = sb * p[3] + t[5];
+    o[0] = sa * q.ax + t[1];
+    o[1] = sa * q.ay + t[2];
+    o[2] = sb * q.bx + t[4];
+    o[3] = sb * q.by + t[5];
   }
 }
 
@@ -246,11 +261,11 @@ __global__ __launch_bounds__(256) void k_verify_hyp(VerifyHdr hd, int n_pairs) {
     if (lane == 0) scores[k] = -INFINITY;
     return;
   }
-  const double* raw = reinterpret_cast<const double*>(hd.ws + e.raw);
+  const float4* raw = reinterpret_cast<const float4*>(hd.ws + e.raw);
   double acc = 0.0;
   for (int i = lane; i < n; i += 64) {
-    const double* q = raw + 4 * (int64_t)i;
-    acc += marginal_w(residual(H, q[0], q[1], q[2], q[3]), hd.sigma_max);
+    const RawPt q = raw_at(raw, i);
+    acc += weight_at(H, q.ax, q.ay, q.bx, q.by, hd.sigma_max);
   }
   acc = wave_sum_d(acc);
   if (lane == 0) scores[k] = acc;
@@ -271,7 +286,7 @@ __global__ __launch_bounds__(256) void k_verify_refine(VerifyHdr hd, int n_pairs
   const VerifyEntry e = hd.table[blockIdx.x];
   const int n = verify_count(e);
   const double* scores = reinterpret_cast<const double*>(hd.ws + e.scores);
-  const double* raw = reinterpret_cast<const double*>(hd.ws + e.raw);
+  const float4* raw = reinterpret_cast<const float4*>(hd.ws + e.raw);
   const double* pts = reinterpret_cast<const double*>(hd.ws + e.pts);
   const double* nrm = reinterpret_cast<const double*>(hd.ws + e.norm);
 
@@ -340,8 +355,8 @@ __global__ __launch_bounds__(256) void k_verify_refine(VerifyHdr hd, int n_pairs
 #pragma unroll
     for (int q = 0; q < 44; ++q) ne[q] = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) {
-      const double* r = raw + 4 * (int64_t)i;
-      const double w = marginal_w(residual(H, r[0], r[1], r[2], r[3]), hd.sigma_max);
+      const RawPt r = raw_at(raw, i);
+      const double w = weight_at(H, r.ax, r.ay, r.bx, r.by, hd.sigma_max);
       const double* p = pts + 4 * (int64_t)i;
       double r1[9], r2[9];
       dlt_rows(p[0], p[1], p[2], p[3], r1, r2);
@@ -401,8 +416,8 @@ __global__ __launch_bounds__(256) void k_verify_refine(VerifyHdr hd, int n_pairs
     for (int q = 0; q < 9; ++q) H2[q] = s_h[q];
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) {
-      const double* r = raw + 4 * (int64_t)i;
-      acc += marginal_w(residual(H2, r[0], r[1], r[2], r[3]), hd.sigma_max);
+      const RawPt r = raw_at(raw, i);
+      acc += weight_at(H2, r.ax, r.ay, r.bx, r.by, hd.sigma_max);
     }
     const double Q2 = block_sum_d(acc, s4);
     if (!(Q2 > Q)) break;
@@ -413,8 +428,8 @@ __global__ __launch_bounds__(256) void k_verify_refine(VerifyHdr hd, int n_pairs
   // outputs
   double cnt = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
-    const double* r = raw + 4 * (int64_t)i;
-    const double w = marginal_w(residual(H, r[0], r[1], r[2], r[3]), hd.sigma_max);
+    const RawPt r = raw_at(raw, i);
+    const double w = weight_at(H, r.ax, r.ay, r.bx, r.by, hd.sigma_max);
     cnt += w > 0.0 ? 1.0 : 0.0;
     if (e.weights) e.weights[i] = (float)w;
   }
