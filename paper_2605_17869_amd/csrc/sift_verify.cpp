@@ -47,7 +47,7 @@ sift_status check(int32_t n, const sift_verify_pair* pairs, int32_t n_hyp) {
 
 struct Layout {
   int64_t table = 0;
-  std::vector<int64_t> pts, raw, norm, scores;
+  std::vector<int64_t> pts, raw, norm, scores, models;
   int64_t bytes = 0;
 };
 
@@ -64,6 +64,8 @@ Layout layout_of(int32_t n, const sift_verify_pair* pairs, int32_t n_hyp) {
     off = align256(off + 8 * 8);
     L.scores.push_back(off);
     off = align256(off + (int64_t)n_hyp * 8);
+    L.models.push_back(off);
+    off = align256(off + (int64_t)n_hyp * 9 * 8);
   }
   L.bytes = off;
   return L;
@@ -133,10 +135,12 @@ sift_status sift_verify_batch(int32_t n, const sift_verify_pair* pairs, const fl
       v.raw = L.raw[first + t];
       v.norm = L.norm[first + t];
       v.scores = L.scores[first + t];
+      v.models = L.models[first + t];
     }
     if ((e = launch_verify_setup(hd, c, stream)) != hipSuccess) return hip_fail(e, "verify setup");
   }
   if ((e = launch_verify_prep(hd, n, stream)) != hipSuccess) return hip_fail(e, "verify prep");
+  if ((e = launch_verify_models(hd, n, stream)) != hipSuccess) return hip_fail(e, "verify models");
   if ((e = launch_verify_hyp(hd, n, stream)) != hipSuccess) return hip_fail(e, "verify hypotheses");
   if ((e = launch_verify_refine(hd, n, stream)) != hipSuccess) return hip_fail(e, "verify refine");
   return SIFT_OK;

@@ -14,6 +14,7 @@ namespace sift {
 
 constexpr int kVerifySetupChunk = 16;  // pair-table entries per setup launch
 constexpr int kVerifyHypPerGroup = 4;  // hypotheses per work-group (one per wave)
+constexpr int kVerifyModelBlock = 64;  // hypotheses per work-group of the model kernel (one per lane)
 
 // One pair as the kernels see it (written by the setup kernel).
 struct VerifyEntry {
@@ -32,6 +33,7 @@ struct VerifyEntry {
   int64_t raw;       // float4 [cap]: pixel (xa, ya, xb, yb), the keypoints' fp32 values
   int64_t norm;      // double [8]: sa, txa, tya, sb, txb, tyb, n (as double), unused
   int64_t scores;    // double [n_hyp]
+  int64_t models;    // double [n_hyp][9]: each hypothesis' model (NaN when there is none)
 };
 
 struct VerifyHdr {
@@ -52,6 +54,7 @@ struct VerifySetupChunk {
 
 hipError_t launch_verify_setup(const VerifyHdr& h, const VerifySetupChunk& c, hipStream_t stream);
 hipError_t launch_verify_prep(const VerifyHdr& h, int n, hipStream_t stream);
+hipError_t launch_verify_models(const VerifyHdr& h, int n, hipStream_t stream);
 hipError_t launch_verify_hyp(const VerifyHdr& h, int n, hipStream_t stream);
 hipError_t launch_verify_refine(const VerifyHdr& h, int n, hipStream_t stream);
 

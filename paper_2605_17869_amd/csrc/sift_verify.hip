@@ -166,34 +166,98 @@ __device__ __forceinline__ RawPt raw_at(const float4* raw, int i) {
   return RawPt{(double)v.x, (double)v.y, (double)v.z, (double)v.w};
 }
 
-// The model of minimal sample k (wave-level; A: 72 doubles of this wave's LDS).
-__device__ bool minimal_model(const VerifyHdr& hd, const VerifyEntry& e, int k, int n, double* A,
-                              double* H) {
-  const int lane = threadIdx.x & 63;
-  const double* pts = reinterpret_cast<const double*>(hd.ws + e.pts);
-  const double* nrm = reinterpret_cast<const double*>(hd.ws + e.norm);
-  int idx[4];
+// solve8_wave for one lane: the same steps in the same order on a system in
+// this lane's registers (A[r][c], augmented column 8), row swaps by selects.
+__device__ __forceinline__ bool solve8_lane(double (&A)[8][9], double* h) {
+  double scale = 0.0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const double u = (double)hd.samples[4 * k + j];
-    const int q = (int)floor(u * (double)n);
-    idx[j] = q < n - 1 ? q : n - 1;
+  for (int r = 0; r < 8; ++r)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) scale = fmax(scale, fabs(A[r][c]));
+  bool ok = scale > 0.0;
+#pragma unroll
+  for (int col = 0; col < 8; ++col) {
+    // pivot row: the first of the largest |A[r][col]|, r >= col
+    int piv = col;
+    double best = fabs(A[col][col]);
+#pragma unroll
+    for (int r = col + 1; r < 8; ++r) {
+      const double v = fabs(A[r][col]);
+      const bool up = v > best;
+      best = up ? v : best;
+      piv = up ? r : piv;
+    }
+    ok = ok && !(best < kPivotEps * scale);
+#pragma unroll
+    for (int r = col + 1; r < 8; ++r) {
+      const bool sw = r == piv;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        const double t = A[col][j];
+        A[col][j] = sw ? A[r][j] : t;
+        A[r][j] = sw ? t : A[r][j];
+      }
+    }
+#pragma unroll
+    for (int r = col + 1; r < 8; ++r) {
+      const double f = A[r][col] / A[col][col];
+#pragma unroll
+      for (int j = col; j < 9; ++j) A[r][j] = A[r][j] - f * A[col][j];
+    }
   }
-  bool distinct = true;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int row = 7; row >= 0; --row) {
+    double acc = A[row][8];
 #pragma unroll
-    for (int j = i + 1; j < 4; ++j) distinct = distinct && idx[i] != idx[j];
-  if (!distinct) return false;
-  if (lane < 4) {
-    const int mine = lane == 0 ? idx[0] : (lane == 1 ? idx[1] : (lane == 2 ? idx[2] : idx[3]));
-    const double* p = pts + 4 * (int64_t)mine;
-    dlt_rows(p[0], p[1], p[2], p[3], A + 18 * lane, A + 18 * lane + 9);
+    for (int j = row + 1; j < 8; ++j) acc = acc - A[row][j] * h[j];
+    h[row] = acc / A[row][row];
   }
-  wave_lds_sync();
-  double h[8];
-  if (!solve8_wave(A, h)) return false;
-  return denormalise(h, nrm, H);
+  return ok;
+}
+
+// The model of every minimal sample, one lane per hypothesis: sample k takes
+// correspondences floor(u[k][j] n) (at most n - 1), j = 0..3; repeated
+// indices give no model, else the DLT rows of the four normalised
+// correspondences are solved (solve8_lane) and the solution moved back to
+// pixels.  Stored for the scoring and refinement kernels; NaN where a sample
+// gives no model.
+__global__ __launch_bounds__(kVerifyModelBlock) void k_verify_models(VerifyHdr hd, int n_pairs) {
+  const int groups = (hd.n_hyp + kVerifyModelBlock - 1) / kVerifyModelBlock;
+  const int p = blockIdx.x / groups;
+  const int k = (blockIdx.x - p * groups) * kVerifyModelBlock + threadIdx.x;
+  if (k >= hd.n_hyp) return;
+  const VerifyEntry e = hd.table[p];
+  const int n = verify_count(e);
+  double* out = reinterpret_cast<double*>(hd.ws + e.models) + 9 * (int64_t)k;
+  double H[9];
+  bool ok = n >= 4;
+  if (ok) {
+    const double* pts = reinterpret_cast<const double*>(hd.ws + e.pts);
+    const double* nrm = reinterpret_cast<const double*>(hd.ws + e.norm);
+    int idx[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const double u = (double)hd.samples[4 * k + j];
+      const int q = (int)floor(u * (double)n);
+      idx[j] = q < n - 1 ? q : n - 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = i + 1; j < 4; ++j) ok = ok && idx[i] != idx[j];
+    if (ok) {
+      double A[8][9];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const double* q = pts + 4 * (int64_t)idx[i];
+        dlt_rows(q[0], q[1], q[2], q[3], A[2 * i], A[2 * i + 1]);
+      }
+      double h[8];
+      ok = solve8_lane(A, h) && denormalise(h, nrm, H);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) out[q] = ok ? H[q] : NAN;
 }
 
 __global__ void k_verify_setup(VerifyHdr hd, VerifySetupChunk c) {
@@ -245,10 +309,9 @@ __global__ __launch_bounds__(256) void k_verify_prep(VerifyHdr hd, int n_pairs) 
   }
 }
 
-// One wave per hypothesis: its minimal model and its score, the sum over the
-// pair's correspondences of the marginal likelihood of the residual.
-__global__ __launch_bounds__(256) void k_verify_hyp(VerifyHdr hd, int n_pairs) {
-  __shared__ double s_a[kVerifyHypPerGroup][72];
+// One wave per hypothesis: its score, the sum over the pair's correspondences
+// of the marginal likelihood of the residual under its stored model.
+__global__ __launch_bounds__(64 * kVerifyHypPerGroup) void k_verify_hyp(VerifyHdr hd, int n_pairs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int p = blockIdx.x / hd.hyp_groups;
   const int k = (blockIdx.x - p * hd.hyp_groups) * kVerifyHypPerGroup + wave;
@@ -256,8 +319,11 @@ __global__ __launch_bounds__(256) void k_verify_hyp(VerifyHdr hd, int n_pairs) {
   const VerifyEntry e = hd.table[p];
   const int n = verify_count(e);
   double* scores = reinterpret_cast<double*>(hd.ws + e.scores);
+  const double* model = reinterpret_cast<const double*>(hd.ws + e.models) + 9 * (int64_t)k;
   double H[9];
-  if (n < 4 || !minimal_model(hd, e, k, n, s_a[wave], H)) {
+#pragma unroll
+  for (int q = 0; q < 9; ++q) H[q] = model[q];
+  if (isnan(H[0])) {
     if (lane == 0) scores[k] = -INFINITY;
     return;
   }
@@ -335,19 +401,13 @@ __global__ __launch_bounds__(256) void k_verify_refine(VerifyHdr hd, int n_pairs
       for (int i = threadIdx.x; i < e.cap; i += 256) e.weights[i] = 0.0f;
     return;
   }
-  // the best model again (wave 0), shared through LDS
-  if (wave == 0) {
-    double H[9];
-    const bool ok = minimal_model(hd, e, bi, n, s_a, H);
-    if (lane == 0) {
-      for (int q = 0; q < 9; ++q) s_h[q] = H[q];
-      s_flag = ok ? 1 : 0;
-    }
-  }
-  __syncthreads();
+  // the best hypothesis' model, as stored
   double H[9];
+  {
+    const double* model = reinterpret_cast<const double*>(hd.ws + e.models) + 9 * (int64_t)bi;
 #pragma unroll
-  for (int q = 0; q < 9; ++q) H[q] = s_h[q];
+    for (int q = 0; q < 9; ++q) H[q] = model[q];
+  }
   double Q = bv;
   for (int it = 0; it < hd.refine_iters; ++it) {
     // weighted normal equations of the DLT rows (upper triangle + rhs)
@@ -452,8 +512,13 @@ hipError_t launch_verify_prep(const VerifyHdr& h, int n, hipStream_t stream) {
   return launch(k_verify_prep, dim3(n), dim3(256), stream, h, n);
 }
 
+hipError_t launch_verify_models(const VerifyHdr& h, int n, hipStream_t stream) {
+  const int groups = (h.n_hyp + kVerifyModelBlock - 1) / kVerifyModelBlock;
+  return launch(k_verify_models, dim3(n * groups), dim3(kVerifyModelBlock), stream, h, n);
+}
+
 hipError_t launch_verify_hyp(const VerifyHdr& h, int n, hipStream_t stream) {
-  return launch(k_verify_hyp, dim3(n * h.hyp_groups), dim3(256), stream, h, n);
+  return launch(k_verify_hyp, dim3(n * h.hyp_groups), dim3(64 * kVerifyHypPerGroup), stream, h, n);
 }
 
 hipError_t launch_verify_refine(const VerifyHdr& h, int n, hipStream_t stream) {
