@@ -38,6 +38,7 @@ hipError_t launch_match_cols(const MatchHdr&, int, int, hipStream_t) { return hi
 hipError_t launch_match_emit(const MatchHdr&, int, float, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_verify_setup(const VerifyHdr&, const VerifySetupChunk&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_verify_prep(const VerifyHdr&, int, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_verify_models(const VerifyHdr&, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_verify_hyp(const VerifyHdr&, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_verify_refine(const VerifyHdr&, int, hipStream_t) { return hipErrorNotSupported; }
 }  // namespace sift
