@@ -14,7 +14,7 @@ from gpu_util import digest, extract, extract_batch, require_gpu, say
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [(97, 129), (480, 640), (333, 70), (53, 61), (56, 205)]
+SIZES = [(97, 129), (480, 640), (333, 70), (53, 61), (56, 205), (64, 2500), (2100, 64)]
 
 
 def run(settings, imgs):
