@@ -419,12 +419,15 @@ def main():
     # (the extraction timings below start from device-resident images)
     pinned = [torch.from_numpy(im).pin_memory() for im in imgs]
     d_imgs = [torch.empty(im.shape, dtype=torch.float32, device=dev) for im in imgs]
-    torch.cuda.synchronize()
-    h0 = time.perf_counter()
-    for d, h in zip(d_imgs, pinned):
-        d.copy_(h, non_blocking=True)
-    torch.cuda.synchronize()
-    h2d_s = time.perf_counter() - h0
+    h2d_passes = []
+    for _ in range(3):       # the first pass also pays the copy engines' set-up
+        torch.cuda.synchronize()
+        h0 = time.perf_counter()
+        for d, h in zip(d_imgs, pinned):
+            d.copy_(h, non_blocking=True)
+        torch.cuda.synchronize()
+        h2d_passes.append(time.perf_counter() - h0)
+    h2d_s = min(h2d_passes[1:])
     h2d_bytes = sum(im.nbytes for im in imgs)
     del pinned
     sizes = [tuple(im.shape) for im in imgs]
@@ -673,7 +676,9 @@ def main():
         "h2d": {"ms": round(h2d_s * 1e3, 2), "bytes": h2d_bytes,
                 "gbs": round(h2d_bytes / h2d_s / 1e9, 2),
                 "images_per_s_with_h2d": round(n / (ms * 1e-3 + h2d_s), 2),
-                "note": "pinned host buffers, one copy per image, before timing; not in value"},
+                "first_pass_ms": round(h2d_passes[0] * 1e3, 2),
+                "note": "pinned host buffers, one copy per image, before timing; best of two "
+                        "passes after a first; not in value"},
         "fp16_storage": fp16,
         "serving": serving,
         "matching": matching,
