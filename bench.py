@@ -375,6 +375,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--blur-chain", type=int, default=0,
                     help="pyramid levels per launch (0: autotuned unless --no-autotune, else 2)")
+    ap.add_argument("--detect-waves", type=int, default=0,
+                    help="waves per detection work-group, 4 or 8 (0: autotuned unless "
+                         "--no-autotune, else 4)")
     ap.add_argument("--n-streams", type=int, default=0,
                     help="sub-batches of a batched call (0: library choice, 1: one launch sequence)")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay timing")
@@ -434,20 +437,24 @@ def main():
     stream = torch.cuda.current_stream()
     tune = None
     tile_rows, n_streams, blur_chain = args.tile_rows, args.n_streams, args.blur_chain
+    detect_waves = args.detect_waves
     if tile_rows == 0 and not args.no_autotune:
         # the launch knobs (chunk-height cap x sub-batch count, then pyramid
-        # levels per launch), timed afresh in the form the line reports (graph
-        # replay, unless --no-graph)
-        probe = sm.Extractor(dict(wl.settings, blur_chain=blur_chain))
+        # levels per launch, then waves per detection work-group), timed afresh
+        # in the form the line reports (graph replay, unless --no-graph)
+        probe = sm.Extractor(dict(wl.settings, blur_chain=blur_chain, detect_waves=detect_waves))
         tune = probe.tune(d_imgs, warmup=1, reps=5, as_graph=not args.no_graph, stream=stream)
         tile_rows = tune["tile_rows"]
         if n_streams == 0:
             n_streams = tune["n_streams"]
         if blur_chain == 0:
             blur_chain = tune["blur_chain"]
+        if detect_waves == 0:
+            detect_waves = tune["detect_waves"]
         del probe
         print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
-    settings = dict(wl.settings, tile_rows=tile_rows, n_streams=n_streams, blur_chain=blur_chain)
+    settings = dict(wl.settings, tile_rows=tile_rows, n_streams=n_streams, blur_chain=blur_chain,
+                    detect_waves=detect_waves)
     ex = sm.Extractor(settings)
     ws = torch.empty(ex.batch_workspace_size(sizes), dtype=torch.uint8, device=dev)
     outs = [ex.alloc_features() for _ in range(n)]
@@ -655,6 +662,7 @@ def main():
         "config": {"workload": wl.name, "images": n, "image_size": (f"{sizes[0][1]}x{sizes[0][0]}" if len(set(sizes)) == 1
                                   else f"mixed, mean {mpix / n:.3f} Mpix"),
                    "tile_rows": tile_rows, "n_streams": n_streams, "blur_chain": blur_chain,
+                   "detect_waves": detect_waves,
                    "upsample": wl.settings["upsample"], "octaves": wl.settings["n_octaves"] +
                    wl.settings["upsample"], "parallelism": "none (one GPU)"},
         "mpix_per_s": round(mpix / (ms * 1e-3), 2),

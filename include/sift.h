@@ -112,6 +112,9 @@ typedef struct {
                                  launch (runs of radius <= 8 that the library has a kernel
                                  for), so the levels between are not read back from memory.
                                  Any value gives bit-identical results (tuning only) */
+  int32_t detect_waves;       /* 0: library choice (4); 4 or 8: waves per work-group of the
+                                 extrema search, which share a band's column segments.
+                                 Either gives bit-identical results (tuning only) */
 } sift_params;
 
 /* One keypoint, 48 bytes.  Keypoints of an image come in canonical order:
@@ -350,14 +353,16 @@ sift_status sift_autotune_batch(const sift_params* p, int32_t n, const float* co
  * Tuning over the launch knobs, with a persisted cache.  sift_autotune
  * times sift_extract_batch on the given batch for every blur chunk-height cap
  * (64, 128, 256, 512) and every sub-batch count (1, 2, 4, 8, at most n) at
- * the settings' blur_chain, then the other pyramid run lengths (1, 2, 3
- * levels per launch) at the best of those -- all of them give bit-identical
- * results -- and returns the fastest in *out.  With cache_path non-NULL it
- * first looks the batch up in that text file (one line per entry: key,
- * tile_rows, n_streams, blur_chain, ms; the last entry of a key wins) and, on
- * a hit, returns the entry without timing (from_cache = 1); after timing it
- * appends the winner.  The key names the device (name, architecture, compute
- * units), the settings other than the three tuned fields, the image count,
+ * the settings' blur_chain and detect_waves, then the other pyramid run
+ * lengths (1, 2, 3 levels per launch) at the best of those, then the other
+ * waves per detection work-group (4 or 8) at the best so far -- all of them
+ * give bit-identical results -- and returns the fastest in *out.  With
+ * cache_path non-NULL it first looks the batch up in that text file (one line
+ * per entry: key, tile_rows, n_streams, blur_chain, detect_waves, ms; the last
+ * entry of a key wins) and, on a hit, returns the entry without timing
+ * (from_cache = 1); after timing it appends the winner.  The key names the
+ * device (name, architecture, compute units), the settings other than the four
+ * tuned fields, the image count,
  * the total input pixels to two significant figures and the execution form:
  * as_graph = 0 times the launch sequence (sift_extract_batch), 1 times
  * replays of it recorded as a graph (sift_graph_*), whose best split can
@@ -371,6 +376,7 @@ typedef struct {
   int32_t from_cache;   /* 1: read from the cache file, nothing timed */
   int32_t n_tried;      /* candidates timed */
   int32_t blur_chain;   /* chosen pyramid levels per launch (1..3) */
+  int32_t detect_waves; /* chosen waves per detection work-group (4 or 8) */
 } sift_tuning;
 
 /* Workspace that every candidate of sift_autotune fits in (a split into more

@@ -150,6 +150,8 @@ sift_status validate_params(const sift_params& p) {
     return fail(SIFT_ERR_INVALID_ARG, "pyramid_fp16 must be 0 or 1");
   if (p.blur_chain < 0 || p.blur_chain > kChainMaxLevels)
     return fail(SIFT_ERR_INVALID_ARG, "blur_chain must be in 0..%d", kChainMaxLevels);
+  if (p.detect_waves != 0 && p.detect_waves != 4 && p.detect_waves != 8)
+    return fail(SIFT_ERR_INVALID_ARG, "detect_waves must be 0, 4 or 8");
   // Window sizes.  A refined keypoint has layer + offset below s + 1/2, so
   // its octave scale stays below sigma0 * 2^((s + 1/2) / s).  The descriptor
   // scans a square of half-side ceil(2.5 * cell * (|cos| + |sin|)) + 1 for
@@ -661,7 +663,9 @@ sift_status launch_stages(const sift_handle* h, const Config& cfg, int32_t n, co
   const int bands = (int)plan.bands;
   // detection reads the s+3 levels once and writes one mask bit per pixel-layer
   prec = prof_begin(kStDetect, (p.s + 3) * level_px_bytes + p.s / 8.0 * all_px, stream);
-  if (bands > 0 && (st = check_hip(launch_detect(ws, hp, n, p, bands, stream), "detect")) != SIFT_OK)
+  const int waves = h->params.detect_waves == 0 ? kDetectWaves : h->params.detect_waves;
+  if (bands > 0 &&
+      (st = check_hip(launch_detect(ws, hp, n, p, waves, bands, stream), "detect")) != SIFT_OK)
     return st;
   prof_end(prec, stream);
   prec = prof_begin(kStCompact, (p.s / 4.0) * all_px, stream);

@@ -185,6 +185,7 @@ std::string tune_key(const sift_params* p, int32_t n, const int32_t* heights, co
   q.tile_rows = 0;
   q.n_streams = 0;
   q.blur_chain = 0;
+  q.detect_waves = 0;
   double px = 0.0;
   for (int i = 0; i < n; ++i) px += (double)heights[i] * widths[i];
   const double mag = px > 0 ? std::pow(10.0, std::floor(std::log10(px)) - 1.0) : 1.0;
@@ -211,7 +212,8 @@ bool cache_lookup(const char* path, const std::string& key, sift_tuning* t) {
     std::string k;
     sift_tuning v;
     std::memset(&v, 0, sizeof v);
-    if (is >> k >> v.tile_rows >> v.n_streams >> v.blur_chain >> v.ms && k == key) {
+    if (is >> k >> v.tile_rows >> v.n_streams >> v.blur_chain >> v.detect_waves >> v.ms &&
+        k == key) {
       *t = v;
       found = true;
     }
@@ -266,7 +268,7 @@ sift_status sift_autotune(const sift_params* p, int32_t n, const float* const* d
   }
   std::memset(out, 0, sizeof *out);
   const std::string key =
-      tune_key(p, n, heights, widths) + (as_graph ? "/graph" : "/eager") + "/v2";
+      tune_key(p, n, heights, widths) + (as_graph ? "/graph" : "/eager") + "/v3";
   if (cache_lookup(cache_path, key, out)) {
     out->from_cache = 1;
     return SIFT_OK;
@@ -284,11 +286,12 @@ sift_status sift_autotune(const sift_params* p, int32_t n, const float* const* d
   sift_status st = SIFT_OK;
   float best = -1.0f;
   // times one candidate; a split the workspace cannot hold is skipped
-  auto try_one = [&](int32_t tile_rows, int32_t n_streams, int32_t chain) {
+  auto try_one = [&](int32_t tile_rows, int32_t n_streams, int32_t chain, int32_t waves) {
     sift_params pp = *p;
     pp.tile_rows = tile_rows;
     pp.n_streams = n_streams;
     pp.blur_chain = chain;
+    pp.detect_waves = waves;
     sift_handle* h = nullptr;
     st = sift_create(&pp, &h);
     if (st != SIFT_OK) return;
@@ -333,20 +336,27 @@ sift_status sift_autotune(const sift_params* p, int32_t n, const float* const* d
       out->tile_rows = tile_rows;
       out->n_streams = n_streams;
       out->blur_chain = chain;
+      out->detect_waves = waves;
       out->ms = t;
     }
   };
-  // chunk height x sub-batch count at the caller's chain setting, then the
-  // other chain lengths at the best of those (the pyramid's levels per launch
-  // barely interact with the split)
+  // chunk height x sub-batch count at the caller's chain and detection
+  // settings, then the other chain lengths at the best of those (the
+  // pyramid's levels per launch barely interact with the split), then the
+  // other waves per detection work-group at the best so far
   const int32_t chain0 = p->blur_chain == 0 ? 2 : p->blur_chain;
+  const int32_t waves0 = p->detect_waves == 0 ? 4 : p->detect_waves;
   for (int c = 0; c < 4 && st == SIFT_OK; ++c)
     for (int q = 0; q < 4 && st == SIFT_OK; ++q)
-      if (streams[q] <= n) try_one(rows[c], streams[q], chain0);
+      if (streams[q] <= n) try_one(rows[c], streams[q], chain0, waves0);
   if (st == SIFT_OK && best >= 0.0f) {
     const int32_t r0 = out->tile_rows, s0 = out->n_streams;
     for (int32_t chain = 1; chain <= 3 && st == SIFT_OK; ++chain)
-      if (chain != chain0) try_one(r0, s0, chain);
+      if (chain != chain0) try_one(r0, s0, chain, waves0);
+  }
+  if (st == SIFT_OK && best >= 0.0f) {
+    const int32_t r0 = out->tile_rows, s0 = out->n_streams, c0 = out->blur_chain;
+    try_one(r0, s0, c0, waves0 == 4 ? 8 : 4);
   }
   hipEventDestroy(a);
   hipEventDestroy(b);
@@ -355,7 +365,7 @@ sift_status sift_autotune(const sift_params* p, int32_t n, const float* const* d
     std::ofstream f(cache_path, std::ios::app);
     if (f)
       f << key << " " << out->tile_rows << " " << out->n_streams << " " << out->blur_chain << " "
-        << out->ms << "\n";
+        << out->detect_waves << " " << out->ms << "\n";
   }
   return SIFT_OK;
 }

@@ -102,13 +102,13 @@ __device__ __forceinline__ void det_load_row(DetRow<S>& d, const char* const* L,
 }
 
 // The rows of one band: per-layer candidate counts into cnt.  H16: the
-// octave's levels are stored as fp16.
-template <int S, bool H16>
+// octave's levels are stored as fp16; W: waves of the work-group.
+template <int S, bool H16, int W>
 __device__ __forceinline__ void detect_band(const char* const* L, unsigned long long* masks,
                                             int hk, int wk, int pk, int nseg, int b, int r_begin,
                                             int r_end, float thr, int* cnt) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int sg = wave; sg < nseg; sg += kDetectWaves) {
+  for (int sg = wave; sg < nseg; sg += W) {
     const int c = b + sg * kSeg + lane - 1;
     const int cl = min(c, wk - 1);
     const bool out_col = lane >= 1 && lane <= kSeg && c < wk - b;
@@ -142,11 +142,11 @@ __device__ __forceinline__ void detect_band(const char* const* L, unsigned long 
 }
 
 // H16MODE: fp16 level storage is on (the first octave stays fp32, so each
-// work-group picks its octave's path).
-template <int S, bool H16MODE>
-__global__ __launch_bounds__(kDetectWaves * 64) void k_detect(char* ws, HdrPtrs hp, int n,
-                                                             DevParams p) {
-  __shared__ int s_cnt[kDetectWaves][S];
+// work-group picks its octave's path).  W: waves per work-group, which share
+// the band's column segments; the counts do not depend on it.
+template <int S, bool H16MODE, int W>
+__global__ __launch_bounds__(W * 64) void k_detect(char* ws, HdrPtrs hp, int n, DevParams p) {
+  __shared__ int s_cnt[W][S];
   const int* bp = hp.band_prefix;
   // bands dealt to the XCDs in contiguous runs (the grid is a multiple of 8):
   // a band's halo rows are its neighbours' rows, read through the same L2
@@ -175,9 +175,9 @@ __global__ __launch_bounds__(kDetectWaves * 64) void k_detect(char* ws, HdrPtrs 
 #pragma unroll
   for (int i = 0; i < S; ++i) cnt[i] = 0;
   if (H16MODE && ov.es == 2)
-    detect_band<S, true>(L, masks, hk, wk, pk, nseg, b, r_begin, r_end, thr, cnt);
+    detect_band<S, true, W>(L, masks, hk, wk, pk, nseg, b, r_begin, r_end, thr, cnt);
   else
-    detect_band<S, false>(L, masks, hk, wk, pk, nseg, b, r_begin, r_end, thr, cnt);
+    detect_band<S, false, W>(L, masks, hk, wk, pk, nseg, b, r_begin, r_end, thr, cnt);
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < S; ++i) s_cnt[wave][i] = cnt[i];
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kDetectWaves * 64) void k_detect(char* ws, HdrPtrs 
     const int i = threadIdx.x;
     int tot = 0;
 #pragma unroll
-    for (int wv = 0; wv < kDetectWaves; ++wv) tot += s_cnt[wv][i];
+    for (int wv = 0; wv < W; ++wv) tot += s_cnt[wv][i];
     int* bc = reinterpret_cast<int*>(ws + e.region + region_tail(e.h, e.w, lc).band_cnt);
     bc[ov.band_base * S + i * ov.nband + band] = tot;
   }
@@ -911,21 +911,21 @@ hipError_t launch_finalize(const HdrPtrs& hp, int n, const DevParams& p, hipStre
   return launch(k_finalize, dim3(1), dim3(64), stream, hp, n, p);
 }
 
-hipError_t launch_detect(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
-                         hipStream_t stream) {
+hipError_t launch_detect(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int waves,
+                         int grid, hipStream_t stream) {
   grid = (grid + kXcds - 1) / kXcds * kXcds;
-#define SIFT_DETECT_CASE(SS)                                                              \
-  case SS:                                                                                \
-    return p.h16 ? launch(k_detect<SS, true>, dim3(grid), dim3(kDetectWaves * 64), stream, \
-                          ws, hp, n, p)                                                    \
-                 : launch(k_detect<SS, false>, dim3(grid), dim3(kDetectWaves * 64), stream, \
-                          ws, hp, n, p);
-  switch (p.s) {
-    SIFT_DETECT_CASE(1) SIFT_DETECT_CASE(2) SIFT_DETECT_CASE(3)
-    SIFT_DETECT_CASE(4) SIFT_DETECT_CASE(5) SIFT_DETECT_CASE(6)
-    default: return hipErrorInvalidValue;
-  }
+#define SIFT_DETECT_CASE(SS, WW)                                                          \
+  if (p.s == SS && waves == WW)                                                           \
+    return p.h16 ? launch(k_detect<SS, true, WW>, dim3(grid), dim3(WW * 64), stream, ws, hp, \
+                          n, p)                                                           \
+                 : launch(k_detect<SS, false, WW>, dim3(grid), dim3(WW * 64), stream, ws, hp, \
+                          n, p);
+#define SIFT_DETECT_WAVES(SS) SIFT_DETECT_CASE(SS, 4) SIFT_DETECT_CASE(SS, 8)
+  SIFT_DETECT_WAVES(1) SIFT_DETECT_WAVES(2) SIFT_DETECT_WAVES(3)
+  SIFT_DETECT_WAVES(4) SIFT_DETECT_WAVES(5) SIFT_DETECT_WAVES(6)
+#undef SIFT_DETECT_WAVES
 #undef SIFT_DETECT_CASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_band_scan(char* ws, const HdrPtrs& hp, int n, const DevParams& p,

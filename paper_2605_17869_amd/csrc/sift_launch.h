@@ -24,8 +24,9 @@ hipError_t launch_blur(const BlurArgs& a, int radius, int grid, hipStream_t stre
 bool chain_supported(int mode, int st, int n_levels, const int* radii);
 hipError_t launch_chain(const ChainArgs& a, int mode, int st, int n_levels, const int* radii,
                         int grid, hipStream_t stream);
-hipError_t launch_detect(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
-                         hipStream_t stream);
+// waves: per work-group, 4 or 8 (anything else: hipErrorInvalidValue)
+hipError_t launch_detect(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int waves,
+                         int grid, hipStream_t stream);
 hipError_t launch_band_scan(char* ws, const HdrPtrs& hp, int n, const DevParams& p,
                          hipStream_t stream);
 hipError_t launch_emit(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,

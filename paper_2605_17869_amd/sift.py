@@ -41,6 +41,7 @@ class SiftParams(ctypes.Structure):
         ("max_candidates", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
         ("n_streams", ctypes.c_int32), ("upsample_max_pixels", ctypes.c_int32),
         ("pyramid_fp16", ctypes.c_int32), ("blur_chain", ctypes.c_int32),
+        ("detect_waves", ctypes.c_int32),
     ]
 
 
@@ -97,7 +98,7 @@ MATCH_DTYPE = np.dtype([("query", "<i4"), ("train", "<i4"), ("similarity", "<f4"
 class SiftTuning(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("n_streams", ctypes.c_int32),
                 ("ms", ctypes.c_float), ("from_cache", ctypes.c_int32), ("n_tried", ctypes.c_int32),
-                ("blur_chain", ctypes.c_int32)]
+                ("blur_chain", ctypes.c_int32), ("detect_waves", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes)
@@ -482,9 +483,9 @@ class Extractor:
 
     def tune(self, images, warmup: int = 1, reps: int = 3, cache_path: str | None = None,
              as_graph: bool = False, outs=None, workspace=None, stream=None) -> dict:
-        """``sift_autotune``: the fastest (tile_rows, n_streams, blur_chain) for this batch
-        run as a launch sequence (or, ``as_graph``, as graph replays), from
-        ``cache_path`` when it holds the batch's key."""
+        """``sift_autotune``: the fastest (tile_rows, n_streams, blur_chain,
+        detect_waves) for this batch run as a launch sequence (or, ``as_graph``,
+        as graph replays), from ``cache_path`` when it holds the batch's key."""
         import torch
         if workspace is None:
             n = len(images)
@@ -502,7 +503,7 @@ class Extractor:
                                       warmup, reps, 1 if as_graph else 0, path, ctypes.byref(t)),
                "sift_autotune")
         return {"tile_rows": t.tile_rows, "n_streams": t.n_streams, "blur_chain": t.blur_chain,
-                "ms": round(t.ms, 4),
+                "detect_waves": t.detect_waves, "ms": round(t.ms, 4),
                 "from_cache": bool(t.from_cache), "candidates_timed": t.n_tried,
                 "timed_as": "graph replay" if as_graph else "launch sequence"}
 

@@ -87,7 +87,9 @@ def test_defaults_and_parameter_validation():
                       (dict(n_octaves=12, upsample=1), 6), (dict(sigma0=9.0), 6),
                       (dict(max_candidates=0), 1), (dict(ori_peak_ratio=1.5), 1),
                       (dict(tile_rows=48), 1), (dict(tile_rows=1024), 1), (dict(n_streams=9), 1),
-                      (dict(blur_chain=-1), 1), (dict(blur_chain=5), 1)]:
+                      (dict(blur_chain=-1), 1), (dict(blur_chain=5), 1),
+                      (dict(detect_waves=2), 1), (dict(detect_waves=16), 1),
+                      (dict(detect_waves=-4), 1)]:
         pp = S.make_params(**bad)
         assert lib.sift_create(ctypes.byref(pp), ctypes.byref(h)) == code, bad
         assert lib.sift_last_error()
@@ -95,6 +97,8 @@ def test_defaults_and_parameter_validation():
         S.Extractor(tile_rows=rows)
     for chain in range(5):
         S.Extractor(blur_chain=chain)
+    for waves in (0, 4, 8):
+        S.Extractor(detect_waves=waves)
     with pytest.raises(S.SiftError):
         S.Extractor(n_scales=0)
     ex = S.Extractor(dsp_scales=[0.5, 1.0, 2.0], rootsift=1)

@@ -53,6 +53,22 @@ def test_chains_do_not_change_results(up, fp16):
             assert run(dict(base, blur_chain=chain, tile_rows=rows), imgs) == ref
 
 
+@pytest.mark.parametrize("up,fp16", [(1, 0), (0, 1)])
+def test_detection_waves_do_not_change_results(up, fp16):
+    """Four or eight waves per detection work-group share a band's column
+    segments differently; candidates, keypoints and descriptors are the same."""
+    require_gpu()
+    imgs = [synth.blob_image(720 + k, h, w, max(4, h * w // 800)) for k, (h, w) in enumerate(SIZES)]
+    base = dict(synth.BASE_SETTINGS, n_octaves=3, upsample=up, pyramid_fp16=fp16)
+    from paper_2605_17869_amd import Extractor
+    outs = {}
+    for waves in (4, 8):
+        say(f"upsample={up} fp16={fp16} detect_waves={waves}")
+        ex = Extractor(dict(base, detect_waves=waves))
+        outs[waves] = [digest(r[0], r[1]) + str(r[2:]) for r in extract_batch(ex, imgs)]
+    assert outs[4] == outs[8]
+
+
 def test_chains_are_launched():
     require_gpu()
     img = synth.blob_image(710, 300, 400, 100)

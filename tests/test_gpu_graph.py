@@ -122,16 +122,16 @@ def test_tuning_cache_round_trip(tmp_path):
     say(f"tuned: {first}")
     assert not first["from_cache"] and first["candidates_timed"] >= 4
     assert first["tile_rows"] in (64, 128, 256, 512) and first["n_streams"] in (1, 2)
-    assert first["blur_chain"] in (1, 2, 3)
+    assert first["blur_chain"] in (1, 2, 3) and first["detect_waves"] in (4, 8)
     again = ex.tune(bufs, warmup=1, reps=1, cache_path=cache)
     assert again["from_cache"] and again["candidates_timed"] == 0
-    knobs = lambda t: (t["tile_rows"], t["n_streams"], t["blur_chain"])
+    knobs = lambda t: (t["tile_rows"], t["n_streams"], t["blur_chain"], t["detect_waves"])
     assert knobs(again) == knobs(first)
     graph = ex.tune(bufs, warmup=1, reps=1, cache_path=cache, as_graph=True)
     assert not graph["from_cache"] and graph["candidates_timed"] >= 4   # its own key
     assert ex.tune(bufs, warmup=1, reps=1, cache_path=cache, as_graph=True)["from_cache"]
     tuned = Extractor(dict(SETTINGS, tile_rows=first["tile_rows"], n_streams=first["n_streams"],
-                           blur_chain=first["blur_chain"]))
+                           blur_chain=first["blur_chain"], detect_waves=first["detect_waves"]))
     ref = [extract(ex, im) for im in imgs]
     feats = tuned.extract_batch(bufs)
     torch.cuda.synchronize()

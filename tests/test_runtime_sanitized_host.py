@@ -24,7 +24,7 @@ hipError_t launch_finalize(const HdrPtrs&, int, const DevParams&, hipStream_t) {
 hipError_t launch_blur(const BlurArgs&, int, int, hipStream_t) { return hipErrorNotSupported; }
 bool chain_supported(int, int, int, const int*) { return false; }
 hipError_t launch_chain(const ChainArgs&, int, int, int, const int*, int, hipStream_t) { return hipErrorNotSupported; }
-hipError_t launch_detect(char*, const HdrPtrs&, int, const DevParams&, int, hipStream_t) { return hipErrorNotSupported; }
+hipError_t launch_detect(char*, const HdrPtrs&, int, const DevParams&, int, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_band_scan(char*, const HdrPtrs&, int, const DevParams&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_emit(char*, const HdrPtrs&, int, const DevParams&, int, hipStream_t) { return hipErrorNotSupported; }
 hipError_t launch_img_prefix(char*, const HdrPtrs&, int, const DevParams&, int, hipStream_t) { return hipErrorNotSupported; }
@@ -68,6 +68,13 @@ int main() {
     CHECK(sift_create(&q, &h) == SIFT_ERR_INVALID_ARG && h == nullptr);
     CHECK(std::strlen(sift_last_error()) > 0);
   }
+  const int bad_waves[3] = {2, 16, -4};
+  for (int b : bad_waves) {
+    sift_params q = p;
+    q.detect_waves = b;
+    sift_handle* h = nullptr;
+    CHECK(sift_create(&q, &h) == SIFT_ERR_INVALID_ARG && h == nullptr);
+  }
   sift_params q0 = p;
   q0.n_scales = 0;
   sift_handle* h0 = nullptr;
@@ -83,12 +90,14 @@ int main() {
         q.upsample = up;
         q.pyramid_fp16 = f16;
         q.blur_chain = chain;
+        q.detect_waves = chain % 2 ? 8 : 4;
         q.n_octaves = 3;
         sift_handle* h = nullptr;
         CHECK(sift_create(&q, &h) == SIFT_OK && h != nullptr);
         if (!h) continue;
         sift_params back;
-        CHECK(sift_get_params(h, &back) == SIFT_OK && back.blur_chain == chain);
+        CHECK(sift_get_params(h, &back) == SIFT_OK && back.blur_chain == chain &&
+              back.detect_waves == q.detect_waves);
         size_t a = 0, b = 0;
         CHECK(sift_workspace_size(h, 480, 640, &a) == SIFT_OK && a > 0);
         CHECK(sift_workspace_size(h, 960, 1280, &b) == SIFT_OK && b > a);
