@@ -29,7 +29,7 @@ constexpr int kNumTileH = 5;       // blur chunk heights 32, 64, 128, 256, 512
 constexpr int kXcds = 8;           // work-groups are dealt round-robin to the XCDs
 constexpr int kMaxParts = 8;       // sub-batches (each with its own header) of one batched call
 constexpr int kBand = 8;           // rows per detection band
-constexpr int kDetectWaves = 4;    // waves of a detection work-group unless the settings say 8
+constexpr int kDetectWaves = 4;    // waves of a detection work-group
 constexpr int kSeg = 62;           // output columns per 64-lane detection segment
 constexpr int kOriBins = 36;
 constexpr int kMaxPeaks = kOriBins / 2;   // strict circular maxima of 36 bins
