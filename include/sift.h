@@ -282,6 +282,19 @@ typedef struct {
 
 sift_status sift_profile_launches(sift_launch_stat* out, int32_t max_out, int32_t* n_out);
 
+/* Bounds checks (tests and debugging; not for production paths).  The same
+ * sources built with -DSIFT_DEBUG_BOUNDS (libsift_mi355x_bounds.so beside
+ * the library) make the pyramid and extraction kernels count every access
+ * that falls outside the memory it belongs to: the image's workspace region,
+ * its input image, its output arrays, an LDS histogram.  The access still
+ * happens (nothing traps); outputs are those of the normal library.
+ * sift_bounds_violations waits for the device (hipDeviceSynchronize), sets
+ * *count to the accesses counted since the last reset, process-wide, and
+ * zeroes the counters when reset is non-zero.  Errors: INVALID_ARG for a null
+ * count; NOT_SUPPORTED from a library built without the checks (*count = 0);
+ * HIP if the device cannot be read. */
+sift_status sift_bounds_violations(int32_t reset, uint64_t* count);
+
 /* Static text for a status code. */
 /*
  * Replayable batches (HIP graphs).  For a batch whose shapes and buffers

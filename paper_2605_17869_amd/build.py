@@ -14,6 +14,8 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libsift_mi355x.so"
+# the same sources with bounds checks in the kernels (-DSIFT_DEBUG_BOUNDS)
+LIB_BOUNDS = PKG / "libsift_mi355x_bounds.so"
 ARCH = "gfx950"
 
 HIP_FLAGS = [
@@ -78,8 +80,9 @@ def mixed_f16_fma(asm_text: str) -> list:
     return bad
 
 
-def device_asm_cmd(src: Path, out: Path) -> list:
-    return [hipcc(), "-x", "hip", *HIP_FLAGS, "--offload-device-only", "-S", str(src), "-o", str(out)]
+def device_asm_cmd(src: Path, out: Path, extra=()) -> list:
+    return [hipcc(), "-x", "hip", *HIP_FLAGS, *extra, "--offload-device-only", "-S", str(src),
+            "-o", str(out)]
 
 
 def check_smem(asm_files):
@@ -108,25 +111,28 @@ def kernel_source_hash(names=("sift_blur.hip", "sift_device.h", "sift_internal.h
     return h.hexdigest()[:16]
 
 
-def build_library(verbose: bool = False) -> Path:
-    """Compile every source into the shared library; returns its path."""
+def build_library(verbose: bool = False, bounds: bool = False) -> Path:
+    """Compile every source into the shared library (with bounds checks in the
+    kernels: the second library); returns its path."""
     objs = []
-    out_dir = PKG / "_build"
+    extra = ["-DSIFT_DEBUG_BOUNDS"] if bounds else []
+    lib = LIB_BOUNDS if bounds else LIB
+    out_dir = PKG / ("_build_bounds" if bounds else "_build")
     out_dir.mkdir(exist_ok=True)
     sources = sorted(CSRC.glob("*.hip")) + sorted(CSRC.glob("*.cpp"))
     procs = []
     asm_files = []
     for src in sources:
         obj = out_dir / (src.name + ".o")
-        cmd = [hipcc(), "-x", "hip", *HIP_FLAGS, "-c", str(src), "-o", str(obj)]
+        cmd = [hipcc(), "-x", "hip", *HIP_FLAGS, *extra, "-c", str(src), "-o", str(obj)]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         objs.append(obj)
         if src.suffix == ".hip":
             asm = out_dir / (src.name + ".s")
-            procs.append((src, subprocess.Popen(device_asm_cmd(src, asm), stdout=subprocess.PIPE,
-                                                stderr=subprocess.STDOUT)))
+            procs.append((src, subprocess.Popen(device_asm_cmd(src, asm, extra),
+                                                stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
             asm_files.append(asm)
     failed = []
     for src, pr in procs:
@@ -139,15 +145,15 @@ def build_library(verbose: bool = False) -> Path:
         msg = "\n".join(f"--- {s}\n{o}" for s, o in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
     check_smem(asm_files)
-    tmp = LIB.with_suffix(".so.tmp")
+    tmp = lib.with_suffix(".so.tmp")
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), *map(str, objs)]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    path = build_library(verbose="-v" in sys.argv)
-    print(path)
+    print(build_library(verbose="-v" in sys.argv))
+    print(build_library(verbose="-v" in sys.argv, bounds=True))

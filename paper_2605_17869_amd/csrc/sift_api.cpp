@@ -1085,6 +1085,24 @@ sift_status sift_profile_stop(sift_stage_stat* stats, int32_t max_stats, int32_t
   return st;
 }
 
+sift_status sift_bounds_violations(int32_t reset, uint64_t* count) {
+  if (!count) return fail(SIFT_ERR_INVALID_ARG, "null argument");
+  *count = 0;
+#ifdef SIFT_DEBUG_BOUNDS
+  hipError_t e = hipDeviceSynchronize();
+  unsigned long long a = 0, b = 0;
+  if (e == hipSuccess) e = bounds_count_blur(&a, reset != 0);
+  if (e == hipSuccess) e = bounds_count_kernels(&b, reset != 0);
+  if (e != hipSuccess) return check_hip(e, "bounds counters");
+  *count = (uint64_t)(a + b);
+  return SIFT_OK;
+#else
+  (void)reset;
+  return fail(SIFT_ERR_NOT_SUPPORTED,
+              "built without bounds checks (libsift_mi355x_bounds.so has them)");
+#endif
+}
+
 const char* sift_status_string(sift_status st) {
   switch (st) {
     case SIFT_OK: return "ok";

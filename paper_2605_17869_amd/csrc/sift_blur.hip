@@ -62,6 +62,9 @@ struct BlurSource {
   float bias;
   int in_h;          // input rows (upsampling)
   int hk;            // rows of the octave (mirroring)
+#ifdef SIFT_DEBUG_BOUNDS
+  Span span;         // the memory the source lies in (bounds checks)
+#endif
 
   // xc: the thread's column of the octave, already mirrored into [0, wk)
   __device__ __forceinline__ void init(char* ws, const ImgEntry& e, const LayoutCfg& lc,
@@ -70,6 +73,9 @@ struct BlurSource {
     const float* src;
     int csh = 0;   // source column = xc << csh
     bias = 0.0f;
+#ifdef SIFT_DEBUG_BOUNDS
+    span = (UP || mode == kSrcImage) ? input_span(e) : region_span(ws, e, lc);
+#endif
     if (UP || mode == kSrcImage) {
       src = e.src;
       sp = 4 * (int64_t)e.src_pitch;
@@ -101,6 +107,8 @@ struct BlurSource {
       const int ya = y >> 1, yb = min(ya + 1, in_h - 1);
       const gchar* r0 = uniform_ptr(gsrc + ya * sp);
       const gchar* r1 = uniform_ptr(gsrc + ((y & 1) ? yb : ya) * sp);
+      SIFT_CHECK_IN(span, r0 + ua, 4);
+      SIFT_CHECK_IN(span, r1 + ub, 4);
       const float va = load_at(r0, ua), vb = load_at(r0, ub);
       const float vc = load_at(r1, ua), vd = load_at(r1, ub);
       float top = va - bias, bot = vc - bias;
@@ -108,6 +116,7 @@ struct BlurSource {
       bot = uo ? (bot + (vd - bias)) * 0.5f : bot;
       return (y & 1) ? (top + bot) * 0.5f : top;
     } else {
+      SIFT_CHECK_IN(span, gsrc + y * sp + bo, ES_S);
       const float v = load_lv<S16>(uniform_ptr(gsrc + y * sp), bo) - bias;
       return ST == 1 ? round_f16(v) : v;
     }
@@ -124,6 +133,8 @@ struct BlurSource {
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       const gchar* rp = uniform_ptr(gsrc + min(s0 + i, in_h - 1) * sp);
+      SIFT_CHECK_IN(span, rp + ua, 4);
+      SIFT_CHECK_IN(span, rp + ub, 4);
       const float va = load_at(rp, ua), vb = load_at(rp, ub);
       const float top = va - bias;
       hrow[i] = uo ? (top + (vb - bias)) * 0.5f : top;
@@ -217,6 +228,7 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
   const int xs = x0 - R + min(t, WI - 1);
   BlurSource<UP, ST> src;
   src.init(a.ws, e, lc, ov, k, a.dst_level, mode, a.p.s, mirror(xs, wk));
+  SIFT_SPAN(rs, region_span(a.ws, e, lc));
   auto gt = [&](int q) { return a.taps[R + q]; };
 
   // window w[i] = source row y0 + m B - R + i of the thread's column
@@ -238,7 +250,10 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
       // that owns the row and the strip that owns the column
 #pragma unroll
       for (int r = 0; r < B; ++r)
-        if (yb + r < y1) store_lv<D16>(uniform_ptr(l0 + (yb + r) * pkb), (uint32_t)xs * ES_D, w[R + r]);
+        if (yb + r < y1) {
+          SIFT_CHECK_IN(rs, l0 + (yb + r) * pkb + (uint32_t)xs * ES_D, ES_D);
+          store_lv<D16>(uniform_ptr(l0 + (yb + r) * pkb), (uint32_t)xs * ES_D, w[R + r]);
+        }
     }
     // vertical pass into LDS block m & 1 (threads past the strip's source
     // columns have nothing to write: their row offset would run past SS)
@@ -274,11 +289,15 @@ __global__ __launch_bounds__(kBlurThreads) void k_blur(BlurArgs a) {
         gchar* row = gdst + y * pkb;   // rows differ across the wave
         if (xo + HB <= wk) {
           // xo is a multiple of 4 and rows start 256-byte aligned
+          SIFT_CHECK_IN(rs, row + (uint32_t)xo * ES_D, HB * ES_D);
           store4_lv<D16>(row, (uint32_t)xo * ES_D, acc);
         } else {
 #pragma unroll
           for (int j = 0; j < HB; ++j)
-            if (xo + j < wk) store_lv<D16>(row, (uint32_t)(xo + j) * ES_D, acc[j]);
+            if (xo + j < wk) {
+              SIFT_CHECK_IN(rs, row + (uint32_t)(xo + j) * ES_D, ES_D);
+              store_lv<D16>(row, (uint32_t)(xo + j) * ES_D, acc[j]);
+            }
         }
       }
     }
@@ -394,6 +413,7 @@ __global__ __launch_bounds__(kBlurThreads, 2) void k_chain(ChainArgs a) {
   const int xs = x0 - HS + t;          // the thread's column in every level
   BlurSource<UP, ST> src;
   src.init(a.ws, e, lc, ov, k, a.lv0, MODE, a.p.s, mirror(xs, wk));
+  SIFT_SPAN(rs, region_span(a.ws, e, lc));
   const int64_t pkb = ES_D * (int64_t)pk;
   const bool own_col = xs >= x0 && xs < x0 + TW && xs < wk;
   gchar* l0 = nullptr;
@@ -457,8 +477,10 @@ __global__ __launch_bounds__(kBlurThreads, 2) void k_chain(ChainArgs a) {
 #pragma unroll
         for (int r = 0; r < B; ++r) {
           const int y = ai + R + r;
-          if (y >= y0 && y < y1)
+          if (y >= y0 && y < y1) {
+            SIFT_CHECK_IN(rs, l0 + y * pkb + (uint32_t)xs * ES_D, ES_D);
             store_lv<D16>(uniform_ptr(l0 + y * pkb), (uint32_t)xs * ES_D, win[0][P][r]);
+          }
         }
       }
       // the next step's newest rows, into the block this step has retired
@@ -490,11 +512,15 @@ __global__ __launch_bounds__(kBlurThreads, 2) void k_chain(ChainArgs a) {
         if (y >= y0 && y < y1 && xo >= x0 && xo < x0 + TW) {
           gchar* row = dst[I] + y * pkb;
           if (xo + 4 <= wk) {
+            SIFT_CHECK_IN(rs, row + (uint32_t)xo * ES_D, 4 * ES_D);
             store4_lv<D16>(row, (uint32_t)xo * ES_D, acc);   // aligned: xo % 4 == 0
           } else {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-              if (xo + j < wk) store_lv<D16>(row, (uint32_t)(xo + j) * ES_D, acc[j]);
+              if (xo + j < wk) {
+                SIFT_CHECK_IN(rs, row + (uint32_t)(xo + j) * ES_D, ES_D);
+                store_lv<D16>(row, (uint32_t)(xo + j) * ES_D, acc[j]);
+              }
           }
         }
         if constexpr (I + 1 < N) {
@@ -605,6 +631,24 @@ hipError_t launch_chain(const ChainArgs& a, int mode, int st, int n_levels, cons
   ChainKernel fn = chain_kernel(mode, st, n_levels, radii);
   if (!fn) return hipErrorInvalidValue;
   return launch(fn, dim3(grid), dim3(kBlurThreads), stream, a);
+}
+
+// The bounds-check counter of this file's kernels (see check_in).
+hipError_t bounds_count_blur(unsigned long long* count, bool reset) {
+#ifdef SIFT_DEBUG_BOUNDS
+  hipError_t e = hipMemcpyFromSymbol(count, HIP_SYMBOL(g_bounds_violations), sizeof *count, 0,
+                                     hipMemcpyDeviceToHost);
+  if (e == hipSuccess && reset) {
+    const unsigned long long zero = 0;
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_bounds_violations), &zero, sizeof zero, 0,
+                          hipMemcpyHostToDevice);
+  }
+  return e;
+#else
+  (void)reset;
+  *count = 0;
+  return hipErrorNotSupported;
+#endif
 }
 
 }  // namespace sift

@@ -39,6 +39,54 @@ __device__ __forceinline__ int* counters_of(char* ws, const ImgEntry& e) {
   return reinterpret_cast<int*>(ws + e.region);
 }
 
+// ---------------------------------------------------------------------------
+// Bounds checks.  A library built with -DSIFT_DEBUG_BOUNDS counts every
+// checked access that falls outside the memory it belongs to (the image's
+// workspace region, its input image, its output arrays, an LDS array) in a
+// counter of each source file, which sift_bounds_violations reads; the
+// access itself still happens.  Without the flag the checks compile to
+// nothing.
+#ifdef SIFT_DEBUG_BOUNDS
+static __device__ unsigned long long g_bounds_violations;
+#endif
+struct Span {
+  uint64_t lo, hi;   // byte addresses [lo, hi)
+};
+__device__ __forceinline__ Span region_span(const char* ws, const ImgEntry& e, const LayoutCfg& lc) {
+  const uint64_t lo = reinterpret_cast<uint64_t>(ws) + (uint64_t)e.region;
+  return Span{lo, lo + (uint64_t)region_tail(e.h, e.w, lc).bytes};
+}
+// the input image: h rows of pitch floats, the last one w wide
+__device__ __forceinline__ Span input_span(const ImgEntry& e) {
+  const uint64_t lo = reinterpret_cast<uint64_t>(e.src);
+  return Span{lo, lo + 4u * ((uint64_t)(e.h - 1) * (uint64_t)e.src_pitch + (uint64_t)e.w)};
+}
+template <typename T>
+__device__ __forceinline__ void check_in(const Span& s, T* p, uint32_t bytes) {
+#ifdef SIFT_DEBUG_BOUNDS
+  const uint64_t a = (uint64_t)(p);
+  if (a < s.lo || a + bytes > s.hi) atomicAdd(&g_bounds_violations, 1ull);
+#endif
+}
+__device__ __forceinline__ void check_index(int64_t i, int64_t n) {
+#ifdef SIFT_DEBUG_BOUNDS
+  if (i < 0 || i >= n) atomicAdd(&g_bounds_violations, 1ull);
+#endif
+}
+// The kernels use these forms, which leave no trace (not even an unused
+// address computation) in a normal build.
+#ifdef SIFT_DEBUG_BOUNDS
+#define SIFT_SPAN(name, expr) const ::sift::Span name = (expr)
+#define SIFT_SPAN_VALUE(expr) (expr)
+#define SIFT_CHECK_IN(span, p, bytes) ::sift::check_in((span), (p), (bytes))
+#define SIFT_CHECK_INDEX(i, n) ::sift::check_index((i), (n))
+#else
+#define SIFT_SPAN(name, expr) ((void)0)
+#define SIFT_SPAN_VALUE(expr) (::sift::Span{0, 0})
+#define SIFT_CHECK_IN(span, p, bytes) ((void)0)
+#define SIFT_CHECK_INDEX(i, n) ((void)0)
+#endif
+
 __device__ __forceinline__ const float* level_ptr(char* ws, const ImgEntry& e, const OctView& ov,
                                                   int level) {
   return reinterpret_cast<const float*>(ws + e.region + ov.level0 + (int64_t)level * ov.plane);

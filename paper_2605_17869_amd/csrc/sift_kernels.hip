@@ -84,10 +84,14 @@ struct DetRow {
 };
 
 template <int S, bool H16>
-__device__ __forceinline__ void det_load_row(DetRow<S>& d, const char* const* L, int64_t off) {
+__device__ __forceinline__ void det_load_row(DetRow<S>& d, const char* const* L, int64_t off,
+                                             const Span& rs) {
   float lv[S + 3];
 #pragma unroll
-  for (int j = 0; j < S + 3; ++j) lv[j] = lv_at<H16>(L[j], off);
+  for (int j = 0; j < S + 3; ++j) {
+    SIFT_CHECK_IN(rs, L[j] + off * (H16 ? 2 : 4), H16 ? 2 : 4);
+    lv[j] = lv_at<H16>(L[j], off);
+  }
 #pragma unroll
   for (int j = 0; j < S + 2; ++j) {
     const float v = lv[j + 1] - lv[j];
@@ -106,17 +110,17 @@ __device__ __forceinline__ void det_load_row(DetRow<S>& d, const char* const* L,
 template <int S, bool H16, int W>
 __device__ __forceinline__ void detect_band(const char* const* L, unsigned long long* masks,
                                             int hk, int wk, int pk, int nseg, int b, int r_begin,
-                                            int r_end, float thr, int* cnt) {
+                                            int r_end, float thr, int* cnt, const Span& rs) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int sg = wave; sg < nseg; sg += W) {
     const int c = b + sg * kSeg + lane - 1;
     const int cl = min(c, wk - 1);
     const bool out_col = lane >= 1 && lane <= kSeg && c < wk - b;
     DetRow<S> w0, w1, w2;
-    det_load_row<S, H16>(w0, L, (int64_t)(r_begin - 1) * pk + cl);
-    det_load_row<S, H16>(w1, L, (int64_t)r_begin * pk + cl);
+    det_load_row<S, H16>(w0, L, (int64_t)(r_begin - 1) * pk + cl, rs);
+    det_load_row<S, H16>(w1, L, (int64_t)r_begin * pk + cl, rs);
     for (int r = r_begin; r < r_end; ++r) {
-      det_load_row<S, H16>(w2, L, (int64_t)(r + 1) * pk + cl);
+      det_load_row<S, H16>(w2, L, (int64_t)(r + 1) * pk + cl, rs);
       float max9[S + 2], min9[S + 2];
 #pragma unroll
       for (int j = 0; j < S + 2; ++j) {
@@ -132,7 +136,10 @@ __device__ __forceinline__ void detect_band(const char* const* L, unsigned long 
         const float nb_min = fminf(fminf(min9[i - 1], min8), min9[i + 1]);
         const bool flag = out_col && fabsf(v) > thr && (v > nb_max || v < nb_min);
         const unsigned long long m = __ballot(flag);
-        if (lane == 0) masks[((int64_t)(i - 1) * hk + r) * nseg + sg] = m;
+        if (lane == 0) {
+          SIFT_CHECK_IN(rs, &masks[((int64_t)(i - 1) * hk + r) * nseg + sg], 8);
+          masks[((int64_t)(i - 1) * hk + r) * nseg + sg] = m;
+        }
         cnt[i - 1] += __popcll(m);
       }
       w0 = w1;
@@ -175,9 +182,11 @@ __global__ __launch_bounds__(W * 64) void k_detect(char* ws, HdrPtrs hp, int n, 
 #pragma unroll
   for (int i = 0; i < S; ++i) cnt[i] = 0;
   if (H16MODE && ov.es == 2)
-    detect_band<S, true, W>(L, masks, hk, wk, pk, nseg, b, r_begin, r_end, thr, cnt);
+    detect_band<S, true, W>(L, masks, hk, wk, pk, nseg, b, r_begin, r_end, thr, cnt,
+                            SIFT_SPAN_VALUE(region_span(ws, e, lc)));
   else
-    detect_band<S, false, W>(L, masks, hk, wk, pk, nseg, b, r_begin, r_end, thr, cnt);
+    detect_band<S, false, W>(L, masks, hk, wk, pk, nseg, b, r_begin, r_end, thr, cnt,
+                             SIFT_SPAN_VALUE(region_span(ws, e, lc)));
   if (lane == 0) {
 #pragma unroll
     for (int i = 0; i < S; ++i) s_cnt[wave][i] = cnt[i];
@@ -189,6 +198,7 @@ __global__ __launch_bounds__(W * 64) void k_detect(char* ws, HdrPtrs hp, int n, 
 #pragma unroll
     for (int wv = 0; wv < W; ++wv) tot += s_cnt[wv][i];
     int* bc = reinterpret_cast<int*>(ws + e.region + region_tail(e.h, e.w, lc).band_cnt);
+    SIFT_CHECK_IN(region_span(ws, e, lc), &bc[ov.band_base * S + i * ov.nband + band], 4);
     bc[ov.band_base * S + i * ov.nband + band] = tot;
   }
 }
@@ -232,6 +242,7 @@ __global__ __launch_bounds__(64) void k_emit(char* ws, HdrPtrs hp, int n, DevPar
   band_owner(e.h, e.w, lc, lb, &k, &band);
   const OctView ov = octave_view(e.h, e.w, lc, k);
   const RegionTail rt = region_tail(e.h, e.w, lc);
+  SIFT_SPAN(rspan, region_span(ws, e, lc));
   const int hk = ov.h, nseg = ov.nseg;
   const int b = p.border;
   const int r_begin = b + band * kBand;
@@ -259,7 +270,10 @@ __global__ __launch_bounds__(64) void k_emit(char* ws, HdrPtrs hp, int n, DevPar
       while (m) {
         const int bit = __ffsll((long long)m) - 1;
         m &= m - 1ull;
-        if (idx < p.max_cand) cands[idx] = make_int4(k, i, r, b + sg * kSeg + bit - 1);
+        if (idx < p.max_cand) {
+          SIFT_CHECK_IN(rspan, &cands[idx], 16);
+          cands[idx] = make_int4(k, i, r, b + sg * kSeg + bit - 1);
+        }
         ++idx;
       }
       base += __shfl(incl, 63, 64);
@@ -321,6 +335,7 @@ __global__ __launch_bounds__(256) void k_refine(char* ws, HdrPtrs hp, int n, Dev
     const int j = g - cp[img];
     const ImgEntry e = tab[img];
     const RegionTail rt = region_tail(e.h, e.w, lc);
+    SIFT_SPAN(rspan, region_span(ws, e, lc));
     const int4 cd = reinterpret_cast<const int4*>(ws + e.region + rt.cands)[j];
     const int k = cd.x;
     int li = cd.y, r = cd.z, c = cd.w;
@@ -351,6 +366,8 @@ __global__ __launch_bounds__(256) void k_refine(char* ws, HdrPtrs hp, int n, Dev
 #pragma unroll
           for (int dc = 0; dc < 3; ++dc) {
             const int64_t off = (int64_t)(r - 1 + dr) * pk + (c - 1 + dc);
+            SIFT_CHECK_IN(rspan, reinterpret_cast<const char*>(La) + off * (h16 ? 2 : 4), h16 ? 2 : 4);
+            SIFT_CHECK_IN(rspan, reinterpret_cast<const char*>(Lb) + off * (h16 ? 2 : 4), h16 ? 2 : 4);
             d[a][dr][dc] = (double)(lv_at(Lb, off, h16) - lv_at(La, off, h16));
           }
       }
@@ -456,6 +473,7 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
     const OctView ov = octave_view(e.h, e.w, lc, kp.k);
     const int hk = ov.h, wk = ov.w, pk = ov.pitch;
     const float* L = level_ptr(ws, e, ov, kp.layer);
+    SIFT_SPAN(rspan, region_span(ws, e, lc));
     const float sw = p.ori_sigma_factor * kp.sigma_oct;
     const int R = (int)floorf(p.ori_radius_factor * sw + 0.5f);
     const float inv2 = 1.0f / (2.0f * sw * sw);
@@ -481,6 +499,8 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
         ddy[u] = dy;
         // samples that do not contribute read the (interior) centre instead
         const int64_t at = (int64_t)(ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c);
+        SIFT_CHECK_IN(rspan, reinterpret_cast<const char*>(L) + (at - pk) * ov.es, ov.es);
+        SIFT_CHECK_IN(rspan, reinterpret_cast<const char*>(L) + (at + pk) * ov.es, ov.es);
         if (H16MODE && ov.es == 2) {
           ga[u] = lv_at<true>(L, at + 1);
           gb[u] = lv_at<true>(L, at - 1);
@@ -513,6 +533,8 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
         // the two bins differ: read both, then write both
         float* c0 = &hist[b0 * OC + (lane & (OC - 1))];
         float* c1 = &hist[b1 * OC + (lane & (OC - 1))];
+        SIFT_CHECK_INDEX(b0 * OC + (lane & (OC - 1)), kOriBins * OC);
+        SIFT_CHECK_INDEX(b1 * OC + (lane & (OC - 1)), kOriBins * OC);
 #pragma unroll
         for (int grp = 0; grp < OG; ++grp) {
           if (ok[u] && lane / OC == grp) {
@@ -644,6 +666,7 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
     const OctView ov = octave_view(e.h, e.w, lc, k);
     const int hk = ov.h, wk = ov.w, pk = ov.pitch;
     const float* L = level_ptr(ws, e, ov, kp.layer);
+    SIFT_SPAN(rspan, region_span(ws, e, lc));
     const gchar* gL = uniform_ptr(reinterpret_cast<const gchar*>(as_global(L)));
     const uint32_t pkb = (uint32_t)pk * 4u;
     const float th = angle * (kTwoPi / 360.0f);
@@ -737,6 +760,9 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
         const int cell = add ? (int)(r0 * 4.0f + c0) : 0;
         float* h0 = &hist[(cell * 8 + io) * DC + col];
         float* h1 = &hist[(cell * 8 + io1) * DC + col];
+        // the eight targets: cells cell .. cell + 5 (rows +0/+1, columns +0/+1)
+        SIFT_CHECK_INDEX((cell * 8 + io) * DC + col, kDescDim * DC);
+        SIFT_CHECK_INDEX(((cell + 5) * 8 + io1) * DC + col, kDescDim * DC);
         float wv[8];
 #pragma unroll
         for (int a = 0; a < 2; ++a) {
@@ -811,6 +837,8 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
         sxy[u] = (dy << 16) | (dx & 0xffff);
         // samples that do not contribute read the (interior) centre instead
         const uint32_t idx = (uint32_t)((ok[u] ? rr : kp.r) * pk + (ok[u] ? cc : kp.c));
+        SIFT_CHECK_IN(rspan, gL + (uint64_t)idx * ov.es - (uint64_t)pk * ov.es, ov.es);
+        SIFT_CHECK_IN(rspan, gL + (uint64_t)idx * ov.es + (uint64_t)pk * ov.es, ov.es);
         if (H16MODE && ov.es == 2) {
           const uint32_t at = idx * 2u, pkh = (uint32_t)pk * 2u;
           ga[u] = load_lv<true>(gL, at + 2u);
@@ -877,6 +905,7 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
       h1 = sqrtf(h1);
     }
     const int slot = q;
+    SIFT_CHECK_INDEX(slot, e.cap);
     float* dout = e.desc + (int64_t)slot * kDescDim;
     dout[lane] = h0;
     dout[lane + 64] = h1;
@@ -971,6 +1000,24 @@ hipError_t launch_describe(char* ws, const HdrPtrs& hp, int n, const DevParams& 
   if (p.n_dsp <= 10) SIFT_DESCRIBE(10);
   SIFT_DESCRIBE(kMaxDsp);
 #undef SIFT_DESCRIBE
+}
+
+// The bounds-check counter of this file's kernels (see check_in).
+hipError_t bounds_count_kernels(unsigned long long* count, bool reset) {
+#ifdef SIFT_DEBUG_BOUNDS
+  hipError_t e = hipMemcpyFromSymbol(count, HIP_SYMBOL(g_bounds_violations), sizeof *count, 0,
+                                     hipMemcpyDeviceToHost);
+  if (e == hipSuccess && reset) {
+    const unsigned long long zero = 0;
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_bounds_violations), &zero, sizeof zero, 0,
+                          hipMemcpyHostToDevice);
+  }
+  return e;
+#else
+  (void)reset;
+  *count = 0;
+  return hipErrorNotSupported;
+#endif
 }
 
 }  // namespace sift

@@ -14,6 +14,8 @@ from pathlib import Path
 import numpy as np
 
 LIB_PATH = Path(__file__).resolve().with_name("libsift_mi355x.so")
+# the same library with bounds checks in its kernels (tests)
+BOUNDS_LIB_PATH = LIB_PATH.with_name("libsift_mi355x_bounds.so")
 MAX_DSP = 16
 DESC_DIM = 128
 
@@ -219,10 +221,12 @@ _SIGNATURES = {
                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                          ctypes.c_void_p]),
     "sift_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sift_bounds_violations": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
     "sift_last_error": (ctypes.c_char_p, []),
 }
 
 _lib = None
+_bounds_lib = None
 
 
 class SiftError(RuntimeError):
@@ -231,29 +235,51 @@ class SiftError(RuntimeError):
         self.status = status
 
 
-def load_library():
-    """Load libsift_mi355x.so (built by ``python -m paper_2605_17869_amd.build``)."""
-    global _lib
+def _open(path: Path):
+    if not path.exists():
+        raise ImportError(f"{path} is missing: build it with "
+                          f"`python -m paper_2605_17869_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch already
+    # loaded (same soname), so the process holds a single runtime
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(str(path))
+    for name, (res, args) in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def load_library(bounds: bool = False):
+    """Load libsift_mi355x.so (built by ``python -m paper_2605_17869_amd.build``),
+    or with ``bounds`` its twin whose kernels count out-of-range accesses."""
+    global _lib, _bounds_lib
+    if bounds:
+        if _bounds_lib is None:
+            _bounds_lib = _open(BOUNDS_LIB_PATH)
+        return _bounds_lib
     if _lib is None:
-        if not LIB_PATH.exists():
-            raise ImportError(f"{LIB_PATH} is missing: build it with "
-                              f"`python -m paper_2605_17869_amd.build`")
-        # torch first: the library then binds to the HIP runtime torch already
-        # loaded (same soname), so the process holds a single runtime
-        import torch  # noqa: F401
-        lib = ctypes.CDLL(str(LIB_PATH))
-        for name, (res, args) in _SIGNATURES.items():
-            fn = getattr(lib, name)
-            fn.restype = res
-            fn.argtypes = args
-        _lib = lib
+        _lib = _open(LIB_PATH)
     return _lib
 
 
 def _check(status: int, where: str):
     if status != SIFT_OK:
-        detail = load_library().sift_last_error().decode()
+        # the message is kept by the library that failed: the loaded ones are asked
+        detail = ""
+        for lib in (_lib, _bounds_lib):
+            if lib is not None and not detail:
+                detail = lib.sift_last_error().decode()
         raise SiftError(status, where, detail)
+
+
+def bounds_violations(reset: bool = True) -> int:
+    """``sift_bounds_violations`` of the bounds-checked library: out-of-range
+    accesses its kernels counted since the last reset (waits for the device)."""
+    n = ctypes.c_uint64()
+    _check(load_library(bounds=True).sift_bounds_violations(1 if reset else 0, ctypes.byref(n)),
+           "sift_bounds_violations")
+    return int(n.value)
 
 
 def make_params(settings: dict | None = None, **overrides) -> SiftParams:
@@ -329,8 +355,10 @@ class Extractor:
     workspace with torch on the current device and enqueues on the current
     (or given) stream."""
 
-    def __init__(self, settings: dict | None = None, **overrides):
-        self.lib = load_library()
+    def __init__(self, settings: dict | None = None, bounds_checked: bool = False, **overrides):
+        # bounds_checked: run on the library whose kernels count out-of-range
+        # accesses (same results; see bounds_violations)
+        self.lib = load_library(bounds=bounds_checked)
         self.params = make_params(settings, **overrides)
         h = ctypes.c_void_p()
         _check(self.lib.sift_create(ctypes.byref(self.params), ctypes.byref(h)), "sift_create")

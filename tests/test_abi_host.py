@@ -20,16 +20,29 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(sift_[a-z_]+)\s*\(", text)))
 
 
-def test_library_exports_every_declared_symbol():
-    lib = S.load_library()
+@pytest.mark.parametrize("bounds", [False, True])
+def test_library_exports_every_declared_symbol(bounds):
+    """Both libraries: the normal one and its bounds-checked twin."""
+    lib = S.load_library(bounds=bounds)
     names = declared_functions()
     assert "sift_extract" in names and "sift_extract_batch" in names and "sift_create" in names
     for name in names:
         assert hasattr(lib, name), name
-    nm = subprocess.run(["nm", "-D", "--defined-only", str(S.LIB_PATH)], capture_output=True,
+    path = S.BOUNDS_LIB_PATH if bounds else S.LIB_PATH
+    nm = subprocess.run(["nm", "-D", "--defined-only", str(path)], capture_output=True,
                         text=True, check=True).stdout
     exported = set(re.findall(r"\bT (sift_\w+)", nm))
     assert set(names) <= exported
+
+
+def test_bounds_query_of_the_normal_library():
+    """The normal library has no bounds checks: it says so before any device call."""
+    lib = S.load_library()
+    n = ctypes.c_uint64(7)
+    assert lib.sift_bounds_violations(1, ctypes.byref(n)) == 6 and n.value == 0   # NOT_SUPPORTED
+    assert b"bounds" in lib.sift_last_error()
+    assert lib.sift_bounds_violations(0, None) == 1                               # INVALID_ARG
+    assert S.load_library(bounds=True).sift_bounds_violations(0, None) == 1
 
 
 PROBE = r"""
