@@ -284,9 +284,10 @@ sift_status sift_profile_launches(sift_launch_stat* out, int32_t max_out, int32_
 
 /* Bounds checks (tests and debugging; not for production paths).  The same
  * sources built with -DSIFT_DEBUG_BOUNDS (libsift_mi355x_bounds.so beside
- * the library) make the pyramid and extraction kernels count every access
- * that falls outside the memory it belongs to: the image's workspace region,
- * its input image, its output arrays, an LDS histogram.  The access still
+ * the library) make the kernels count every access that falls outside the
+ * memory it belongs to: an image's workspace region, its input image, its
+ * output arrays, an LDS histogram; a pair's descriptors, summaries, matches,
+ * correspondences, hypotheses and models.  The access still
  * happens (nothing traps); outputs are those of the normal library.
  * sift_bounds_violations waits for the device (hipDeviceSynchronize), sets
  * *count to the accesses counted since the last reset, process-wide, and

@@ -1090,11 +1090,13 @@ sift_status sift_bounds_violations(int32_t reset, uint64_t* count) {
   *count = 0;
 #ifdef SIFT_DEBUG_BOUNDS
   hipError_t e = hipDeviceSynchronize();
-  unsigned long long a = 0, b = 0;
+  unsigned long long a = 0, b = 0, c = 0, d = 0;
   if (e == hipSuccess) e = bounds_count_blur(&a, reset != 0);
   if (e == hipSuccess) e = bounds_count_kernels(&b, reset != 0);
+  if (e == hipSuccess) e = bounds_count_match(&c, reset != 0);
+  if (e == hipSuccess) e = bounds_count_verify(&d, reset != 0);
   if (e != hipSuccess) return check_hip(e, "bounds counters");
-  *count = (uint64_t)(a + b);
+  *count = (uint64_t)(a + b + c + d);
   return SIFT_OK;
 #else
   (void)reset;

@@ -43,11 +43,13 @@ hipError_t launch_ori_scan(char* ws, const HdrPtrs& hp, int n, const DevParams& 
 hipError_t launch_describe(char* ws, const HdrPtrs& hp, int n, const DevParams& p, int grid,
                          hipStream_t stream);
 
-// Bounds-check counters of the pyramid and extraction kernels (libraries
+// Bounds-check counters of the kernels of each source file (libraries
 // built with -DSIFT_DEBUG_BOUNDS; hipErrorNotSupported otherwise): the count
 // of out-of-range accesses since the last reset, zeroed after reading when
 // `reset`.
 hipError_t bounds_count_blur(unsigned long long* count, bool reset);
 hipError_t bounds_count_kernels(unsigned long long* count, bool reset);
+hipError_t bounds_count_match(unsigned long long* count, bool reset);
+hipError_t bounds_count_verify(unsigned long long* count, bool reset);
 
 }  // namespace sift

@@ -136,6 +136,7 @@ __global__ __launch_bounds__(256) void k_match_rows(MatchHdr h, int n) {
   for (int ta = 0; ta < 4; ++ta) {
     const int ia = row0 + 64 * ahalf + 16 * ta + li;
     const float* arow = e.desc_a + (int64_t)(ia < na ? ia : 0) * kMatchDim;
+    SIFT_CHECK_INDEX(ia < na ? ia : 0, e.cap_a);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) fa[ta][kk] = load_half8(arow, 32 * kk + 8 * gq, ia < na);
   }
@@ -154,6 +155,7 @@ __global__ __launch_bounds__(256) void k_match_rows(MatchHdr h, int n) {
       const int jr = t >> 1, k0 = 64 * (t & 1);
       const int jb = col0 + jr;
       const float* brow = e.desc_b + (int64_t)(jb < nb ? jb : 0) * kMatchDim;
+      SIFT_CHECK_INDEX(jb < nb ? jb : 0, e.cap_b);
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         *reinterpret_cast<half8*>(&s_b[jr * kBStride + k0 + 8 * q]) =
@@ -208,8 +210,10 @@ __global__ __launch_bounds__(256) void k_match_rows(MatchHdr h, int n) {
       if (gq == 0) s_part[ahalf][64 * bhalf + 16 * tb + li] = c;
     }
     __syncthreads();
-    if (t < kMatchTile && col0 + t < nb)
+    if (t < kMatchTile && col0 + t < nb) {
+      SIFT_CHECK_INDEX((int64_t)(col0 + t) * e.rtiles + rt, (int64_t)e.cap_b * e.rtiles);
       colpart[(int64_t)(col0 + t) * e.rtiles + rt] = top2_merge(s_part[0][t], s_part[1][t]);
+    }
   }
   // rows: merge the 16 lanes of each row, then the two b halves
 #pragma unroll
@@ -229,7 +233,10 @@ __global__ __launch_bounds__(256) void k_match_rows(MatchHdr h, int n) {
       for (int r = 0; r < 4; ++r) s_part[bhalf][64 * ahalf + 16 * ta + 4 * gq + r] = rs[ta][r];
   }
   __syncthreads();
-  if (t < kMatchTile && row0 + t < na) rowbest[row0 + t] = top2_merge(s_part[0][t], s_part[1][t]);
+  if (t < kMatchTile && row0 + t < na) {
+    SIFT_CHECK_INDEX(row0 + t, e.cap_a);
+    rowbest[row0 + t] = top2_merge(s_part[0][t], s_part[1][t]);
+  }
 }
 
 // b_j's nearest in a: merge of its per-row-tile summaries (one thread per j).
@@ -244,7 +251,11 @@ __global__ __launch_bounds__(kMatchColBlock) void k_match_cols(MatchHdr h, int n
   const Top2* colpart = reinterpret_cast<const Top2*>(h.ws + e.colpart);
   Top2 c = top2_empty();
   const int used = (na + kMatchTile - 1) / kMatchTile;
-  for (int rt = 0; rt < used; ++rt) c = top2_merge(c, colpart[(int64_t)j * e.rtiles + rt]);
+  for (int rt = 0; rt < used; ++rt) {
+    SIFT_CHECK_INDEX((int64_t)j * e.rtiles + rt, (int64_t)e.cap_b * e.rtiles);
+    c = top2_merge(c, colpart[(int64_t)j * e.rtiles + rt]);
+  }
+  SIFT_CHECK_INDEX(j, e.cap_b);
   reinterpret_cast<Top2*>(h.ws + e.colbest)[j] = c;
 }
 
@@ -273,9 +284,11 @@ __global__ __launch_bounds__(256) void k_match_emit(MatchHdr h, int n, float rat
     bool keep = false;
     Top2 rb = top2_empty();
     if (i < rows) {
+      SIFT_CHECK_INDEX(i, e.cap_a);
       rb = rowbest[i];
       const int j = rb.i1;
       if (j >= 0 && j < nb) {
+        SIFT_CHECK_INDEX(j, e.cap_b);
         const Top2 cb = colbest[j];
         keep = cb.i1 == i && ratio_pass(rb, ratio_sq) && ratio_pass(cb, ratio_sq);
       }
@@ -288,6 +301,7 @@ __global__ __launch_bounds__(256) void k_match_emit(MatchHdr h, int n, float rat
       m.train = rb.i1;
       m.similarity = rb.v1;
       m.distance = sqrtf(sq_dist(rb.v1));
+      SIFT_CHECK_INDEX(base + ex, e.capacity);
       e.matches[base + ex] = m;
     }
     base += tot;
@@ -313,6 +327,24 @@ hipError_t launch_match_cols(const MatchHdr& h, int n, int grid, hipStream_t str
 
 hipError_t launch_match_emit(const MatchHdr& h, int n, float ratio_sq, hipStream_t stream) {
   return launch(k_match_emit, dim3(n), dim3(256), stream, h, n, ratio_sq);
+}
+
+// The bounds-check counter of this file's kernels (see check_index).
+hipError_t bounds_count_match(unsigned long long* count, bool reset) {
+#ifdef SIFT_DEBUG_BOUNDS
+  hipError_t e = hipMemcpyFromSymbol(count, HIP_SYMBOL(g_bounds_violations), sizeof *count, 0,
+                                     hipMemcpyDeviceToHost);
+  if (e == hipSuccess && reset) {
+    const unsigned long long zero = 0;
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_bounds_violations), &zero, sizeof zero, 0,
+                          hipMemcpyHostToDevice);
+  }
+  return e;
+#else
+  (void)reset;
+  *count = 0;
+  return hipErrorNotSupported;
+#endif
 }
 
 }  // namespace sift

@@ -228,6 +228,7 @@ __global__ __launch_bounds__(kVerifyModelBlock) void k_verify_models(VerifyHdr h
   if (k >= hd.n_hyp) return;
   const VerifyEntry e = hd.table[p];
   const int n = verify_count(e);
+  SIFT_CHECK_INDEX(k, hd.n_hyp);
   double* out = reinterpret_cast<double*>(hd.ws + e.models) + 9 * (int64_t)k;
   double H[9];
   bool ok = n >= 4;
@@ -237,6 +238,7 @@ __global__ __launch_bounds__(kVerifyModelBlock) void k_verify_models(VerifyHdr h
     int idx[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
+      SIFT_CHECK_INDEX(4 * k + j, 4 * (int64_t)hd.n_hyp);
       const double u = (double)hd.samples[4 * k + j];
       const int q = (int)floor(u * (double)n);
       idx[j] = q < n - 1 ? q : n - 1;
@@ -276,6 +278,7 @@ __global__ __launch_bounds__(256) void k_verify_prep(VerifyHdr hd, int n_pairs) 
   double* nrm = reinterpret_cast<double*>(hd.ws + e.norm);
   double sx[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = threadIdx.x; i < n; i += 256) {
+    SIFT_CHECK_INDEX(i, e.cap);
     const sift_match m = e.matches[i];
     const sift_keypoint ka = e.kp_a[m.query], kb = e.kp_b[m.train];
     raw[i] = make_float4(ka.x, ka.y, kb.x, kb.y);
@@ -289,6 +292,7 @@ __global__ __launch_bounds__(256) void k_verify_prep(VerifyHdr hd, int n_pairs) 
   __syncthreads();
   double da = 0.0, db = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
+    SIFT_CHECK_INDEX(i, e.cap);
     const RawPt q = raw_at(raw, i);
     const double xa = q.ax - c[0], ya = q.ay - c[1], xb = q.bx - c[2], yb = q.by - c[3];
     da += sqrt(xa * xa + ya * ya);
@@ -300,6 +304,7 @@ __global__ __launch_bounds__(256) void k_verify_prep(VerifyHdr hd, int n_pairs) 
   const double t[6] = {sa, -sa * c[0], -sa * c[1], sb, -sb * c[2], -sb * c[3]};
   if (threadIdx.x < 6) nrm[threadIdx.x] = t[threadIdx.x];
   for (int i = threadIdx.x; i < n; i += 256) {
+    SIFT_CHECK_INDEX(i, e.cap);
     const RawPt q = raw_at(raw, i);
     double* o = pts + 4 * (int64_t)i;
     o[0] = sa * q.ax + t[1];
@@ -319,6 +324,7 @@ __global__ __launch_bounds__(64 * kVerifyHypPerGroup) void k_verify_hyp(VerifyHd
   const VerifyEntry e = hd.table[p];
   const int n = verify_count(e);
   double* scores = reinterpret_cast<double*>(hd.ws + e.scores);
+  SIFT_CHECK_INDEX(k, hd.n_hyp);
   const double* model = reinterpret_cast<const double*>(hd.ws + e.models) + 9 * (int64_t)k;
   double H[9];
 #pragma unroll
@@ -330,6 +336,7 @@ __global__ __launch_bounds__(64 * kVerifyHypPerGroup) void k_verify_hyp(VerifyHd
   const float4* raw = reinterpret_cast<const float4*>(hd.ws + e.raw);
   double acc = 0.0;
   for (int i = lane; i < n; i += 64) {
+    SIFT_CHECK_INDEX(i, e.cap);
     const RawPt q = raw_at(raw, i);
     acc += weight_at(H, q.ax, q.ay, q.bx, q.by, hd.sigma_max);
   }
@@ -404,6 +411,7 @@ __global__ __launch_bounds__(256) void k_verify_refine(VerifyHdr hd, int n_pairs
   // the best hypothesis' model, as stored
   double H[9];
   {
+    SIFT_CHECK_INDEX(bi, hd.n_hyp);
     const double* model = reinterpret_cast<const double*>(hd.ws + e.models) + 9 * (int64_t)bi;
 #pragma unroll
     for (int q = 0; q < 9; ++q) H[q] = model[q];
@@ -415,6 +423,7 @@ __global__ __launch_bounds__(256) void k_verify_refine(VerifyHdr hd, int n_pairs
 #pragma unroll
     for (int q = 0; q < 44; ++q) ne[q] = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) {
+      SIFT_CHECK_INDEX(i, e.cap);
       const RawPt r = raw_at(raw, i);
       const double w = weight_at(H, r.ax, r.ay, r.bx, r.by, hd.sigma_max);
       const double* p = pts + 4 * (int64_t)i;
@@ -476,6 +485,7 @@ __global__ __launch_bounds__(256) void k_verify_refine(VerifyHdr hd, int n_pairs
     for (int q = 0; q < 9; ++q) H2[q] = s_h[q];
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) {
+      SIFT_CHECK_INDEX(i, e.cap);
       const RawPt r = raw_at(raw, i);
       acc += weight_at(H2, r.ax, r.ay, r.bx, r.by, hd.sigma_max);
     }
@@ -488,9 +498,11 @@ __global__ __launch_bounds__(256) void k_verify_refine(VerifyHdr hd, int n_pairs
   // outputs
   double cnt = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
+    SIFT_CHECK_INDEX(i, e.cap);
     const RawPt r = raw_at(raw, i);
     const double w = weight_at(H, r.ax, r.ay, r.bx, r.by, hd.sigma_max);
     cnt += w > 0.0 ? 1.0 : 0.0;
+    SIFT_CHECK_INDEX(i, e.cap);
     if (e.weights) e.weights[i] = (float)w;
   }
   if (e.weights)
@@ -523,6 +535,24 @@ hipError_t launch_verify_hyp(const VerifyHdr& h, int n, hipStream_t stream) {
 
 hipError_t launch_verify_refine(const VerifyHdr& h, int n, hipStream_t stream) {
   return launch(k_verify_refine, dim3(n), dim3(256), stream, h, n);
+}
+
+// The bounds-check counter of this file's kernels (see check_index).
+hipError_t bounds_count_verify(unsigned long long* count, bool reset) {
+#ifdef SIFT_DEBUG_BOUNDS
+  hipError_t e = hipMemcpyFromSymbol(count, HIP_SYMBOL(g_bounds_violations), sizeof *count, 0,
+                                     hipMemcpyDeviceToHost);
+  if (e == hipSuccess && reset) {
+    const unsigned long long zero = 0;
+    e = hipMemcpyToSymbol(HIP_SYMBOL(g_bounds_violations), &zero, sizeof zero, 0,
+                          hipMemcpyHostToDevice);
+  }
+  return e;
+#else
+  (void)reset;
+  *count = 0;
+  return hipErrorNotSupported;
+#endif
 }
 
 }  // namespace sift

@@ -762,15 +762,16 @@ def _desc_arg(desc, count):
     return desc.data_ptr() if desc.shape[0] else None, cptr, int(desc.shape[0])
 
 
-def match_batch(pairs, ratio: float = 0.8, workspace=None, stream=None, outs=None) -> list:
+def match_batch(pairs, ratio: float = 0.8, workspace=None, stream=None, outs=None,
+                bounds_checked: bool = False) -> list:
     """``sift_match_batch`` over pairs of (desc_a, count_a, desc_b, count_b):
     descriptors are float32 CUDA tensors [cap, 128]; a count is a one-element
     int32 CUDA tensor holding the rows in use (e.g. ``Features.counters[0:1]``)
     or None for all rows.  Returns one ``Matches`` per pair (enqueued on the
     current or given stream); ``outs`` reuses the ``Matches`` of an earlier call
-    on pairs of the same sizes."""
+    on pairs of the same sizes; ``bounds_checked`` runs the bounds-checked library."""
     import torch
-    lib = load_library()
+    lib = load_library(bounds=bounds_checked)
     n = len(pairs)
     arr = (SiftMatchPair * n)()
     reuse = outs is not None
@@ -822,14 +823,15 @@ class Verification:
 
 
 def verify_batch(pairs, samples, sigma_max: float = 2.0, refine_iters: int = 5, workspace=None,
-                 stream=None, outs=None) -> list:
+                 stream=None, outs=None, bounds_checked: bool = False) -> list:
     """``sift_verify_batch`` over pairs of (kp_a, kp_b, matches, n_matches):
     keypoint tensors as ``Features.keypoints`` (int32 [cap, 12]), matches as
     ``Matches.records`` (int32 [cap, 4]) and n_matches a one-element int32
     tensor (e.g. ``Matches.counters[0:1]``) or None for every row; ``samples``
-    a float32 CUDA tensor [n_hyp, 4] of numbers in [0, 1)."""
+    a float32 CUDA tensor [n_hyp, 4] of numbers in [0, 1); ``bounds_checked`` runs the
+    bounds-checked library."""
     import torch
-    lib = load_library()
+    lib = load_library(bounds=bounds_checked)
     if samples.dim() != 2 or samples.shape[1] != 4 or samples.dtype != torch.float32 \
             or not samples.is_cuda or not samples.is_contiguous():
         raise ValueError("samples must be a contiguous float32 CUDA tensor [n_hyp, 4]")

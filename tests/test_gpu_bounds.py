@@ -41,3 +41,58 @@ def test_no_access_out_of_bounds(name, over):
     say(f"{name}: {n} out-of-range accesses")
     assert n == 0
     assert got == ref
+
+
+def test_matcher_and_verifier_in_bounds():
+    """Matching (ragged row tiles, device counts below capacity, single rows)
+    and verification (counts below capacity, too few correspondences) on the
+    bounds-checked library: no access out of range, the same bits."""
+    import numpy as np
+    torch = require_gpu()
+    from paper_2605_17869_amd import bounds_violations, match_batch, verify_batch
+
+    sets = [synth.descriptor_sets(s, na, nb, nc, 0.12)[:2]
+            for s, na, nb, nc in [(950, 129, 257, 100), (951, 1, 5, 1), (952, 700, 600, 400)]]
+    counts = [None, None, (450, 333)]
+
+    def matches(bounds):
+        args = []
+        for (a, b), c in zip(sets, counts):
+            ta = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+            tb = torch.from_numpy(np.ascontiguousarray(b, dtype=np.float32)).cuda()
+            ca = cb = None
+            if c is not None:
+                ca = torch.tensor([c[0]], dtype=torch.int32, device="cuda")
+                cb = torch.tensor([c[1]], dtype=torch.int32, device="cuda")
+            args.append((ta, ca, tb, cb))
+        out = match_batch(args, bounds_checked=bounds)
+        torch.cuda.synchronize()
+        return [(m.host()[0].tobytes(), m.host()[1]) for m in out]
+
+    def verified(bounds):
+        pairs = []
+        for seed, n, cnt in [(960, 500, 321), (961, 300, None), (962, 3, None)]:
+            a, b, _, _ = synth.homography_pairs(seed, n, 0.3, 0.5)
+            ka = np.zeros((n, 12), np.int32)
+            kb = np.zeros((n, 12), np.int32)
+            ka.view(np.float32)[:, 0:2] = a.astype(np.float32)
+            kb.view(np.float32)[:, 0:2] = b.astype(np.float32)
+            m = np.zeros((n, 4), np.int32)
+            m[:, 0] = np.arange(n)
+            m[:, 1] = np.arange(n)
+            c = None if cnt is None else torch.tensor([cnt], dtype=torch.int32, device="cuda")
+            pairs.append((torch.from_numpy(ka).cuda(), torch.from_numpy(kb).cuda(),
+                          torch.from_numpy(m).cuda(), c))
+        u = torch.from_numpy(synth.sample_numbers(963, 1500)).cuda()
+        out = verify_batch(pairs, u, bounds_checked=bounds)
+        torch.cuda.synchronize()
+        return [repr([np.asarray(x).tobytes() if isinstance(x, np.ndarray) else x
+                      for x in r.host()]) for r in out]
+
+    say("bounds-checked matching and verification")
+    bounds_violations(reset=True)
+    assert matches(True) == matches(False)
+    assert verified(True) == verified(False)
+    n = bounds_violations(reset=True)
+    say(f"matching and verification: {n} out-of-range accesses")
+    assert n == 0
