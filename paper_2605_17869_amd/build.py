@@ -111,31 +111,33 @@ def kernel_source_hash(names=("sift_blur.hip", "sift_device.h", "sift_internal.h
     return h.hexdigest()[:16]
 
 
-def build_library(verbose: bool = False, bounds: bool = False) -> Path:
-    """Compile every source into the shared library (with bounds checks in the
-    kernels: the second library); returns its path."""
-    objs = []
+def _start(verbose: bool, bounds: bool) -> dict:
+    """Start the compiles of one library (objects and device assembly)."""
     extra = ["-DSIFT_DEBUG_BOUNDS"] if bounds else []
-    lib = LIB_BOUNDS if bounds else LIB
     out_dir = PKG / ("_build_bounds" if bounds else "_build")
     out_dir.mkdir(exist_ok=True)
-    sources = sorted(CSRC.glob("*.hip")) + sorted(CSRC.glob("*.cpp"))
-    procs = []
-    asm_files = []
-    for src in sources:
+    job = {"lib": LIB_BOUNDS if bounds else LIB, "objs": [], "asm": [], "procs": []}
+    for src in sorted(CSRC.glob("*.hip")) + sorted(CSRC.glob("*.cpp")):
         obj = out_dir / (src.name + ".o")
         cmd = [hipcc(), "-x", "hip", *HIP_FLAGS, *extra, "-c", str(src), "-o", str(obj)]
         if verbose:
             print(" ".join(cmd), flush=True)
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        objs.append(obj)
+        job["procs"].append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,
+                                                   stderr=subprocess.STDOUT)))
+        job["objs"].append(obj)
         if src.suffix == ".hip":
             asm = out_dir / (src.name + ".s")
-            procs.append((src, subprocess.Popen(device_asm_cmd(src, asm, extra),
-                                                stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-            asm_files.append(asm)
+            job["procs"].append((src, subprocess.Popen(device_asm_cmd(src, asm, extra),
+                                                       stdout=subprocess.PIPE,
+                                                       stderr=subprocess.STDOUT)))
+            job["asm"].append(asm)
+    return job
+
+
+def _finish(job: dict, verbose: bool) -> Path:
+    """Wait for the compiles, lint the device assembly, link the library."""
     failed = []
-    for src, pr in procs:
+    for src, pr in job["procs"]:
         out, _ = pr.communicate()
         if pr.returncode != 0:
             failed.append((src, out.decode(errors="replace")))
@@ -144,9 +146,11 @@ def build_library(verbose: bool = False, bounds: bool = False) -> Path:
     if failed:
         msg = "\n".join(f"--- {s}\n{o}" for s, o in failed)
         raise RuntimeError(f"hipcc failed:\n{msg}")
-    check_smem(asm_files)
+    check_smem(job["asm"])
+    lib = job["lib"]
     tmp = lib.with_suffix(".so.tmp")
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp), *map(str, objs)]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", str(tmp),
+           *map(str, job["objs"])]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
@@ -154,6 +158,18 @@ def build_library(verbose: bool = False, bounds: bool = False) -> Path:
     return lib
 
 
+def build_library(verbose: bool = False, bounds: bool = False) -> Path:
+    """Compile every source into the shared library (with bounds checks in the
+    kernels: the second library); returns its path."""
+    return _finish(_start(verbose, bounds), verbose)
+
+
+def build_all(verbose: bool = False) -> list:
+    """Both libraries, their compiles run side by side; returns their paths."""
+    jobs = [_start(verbose, False), _start(verbose, True)]
+    return [_finish(j, verbose) for j in jobs]
+
+
 if __name__ == "__main__":
-    print(build_library(verbose="-v" in sys.argv))
-    print(build_library(verbose="-v" in sys.argv, bounds=True))
+    for path in build_all(verbose="-v" in sys.argv):
+        print(path)
