@@ -507,6 +507,7 @@ HdrPtrs header_ptrs(char* ws, int n) {
   hp.band_prefix = reinterpret_cast<int*>(ws + hd.band_prefix);
   hp.cand_prefix = reinterpret_cast<int*>(ws + hd.cand_prefix);
   hp.kp_prefix = reinterpret_cast<int*>(ws + hd.kp_prefix);
+  hp.queue = reinterpret_cast<int*>(ws + hd.queue);
   return hp;
 }
 

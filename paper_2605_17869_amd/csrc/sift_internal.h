@@ -30,6 +30,7 @@ constexpr int kXcds = 8;           // work-groups are dealt round-robin to the X
 constexpr int kMaxParts = 8;       // sub-batches (each with its own header) of one batched call
 constexpr int kBand = 8;           // rows per detection band
 constexpr int kDetectWaves = 4;    // waves of a detection work-group
+constexpr int kQueues = 1;         // work counters: descriptor
 constexpr int kSeg = 62;           // output columns per 64-lane detection segment
 constexpr int kOriBins = 36;
 constexpr int kMaxPeaks = kOriBins / 2;   // strict circular maxima of 36 bins
@@ -209,6 +210,7 @@ struct Header {
   int64_t band_prefix;     // int32 [n + 1]
   int64_t cand_prefix;     // int32 [n + 1]: refined candidates per image
   int64_t kp_prefix;       // int32 [n + 1]: described keypoints per image
+  int64_t queue;           // int32 [kQueues]: next work item of the per-keypoint kernels
   int64_t bytes;
 };
 
@@ -223,6 +225,7 @@ struct HdrPtrs {
   int* band_prefix;        // int32 [n + 1]
   int* cand_prefix;        // int32 [n + 1]
   int* kp_prefix;          // int32 [n + 1]
+  int* queue;              // int32 [kQueues]
 };
 
 SIFT_HD void make_header(int n, Header* hd) {
@@ -237,6 +240,8 @@ SIFT_HD void make_header(int n, Header* hd) {
   off = align_up(off + (int64_t)(n + 1) * 4, 256);
   hd->kp_prefix = off;
   off = align_up(off + (int64_t)(n + 1) * 4, 256);
+  hd->queue = off;
+  off = align_up(off + (int64_t)kQueues * 4, 256);
   hd->bytes = off;
 }
 

@@ -65,6 +65,7 @@ __global__ void k_finalize(HdrPtrs hp, int n, DevParams p) {
       if (lane == t) run += chunk;
     }
   }
+  if (lane < kQueues) hp.queue[lane] = 0;   // the work counters of this launch sequence
 }
 
 // ---------------------------------------------------------------------------
@@ -436,6 +437,19 @@ __global__ __launch_bounds__(256) void k_refine(char* ws, HdrPtrs hp, int n, Dev
 // neighbours.
 
 // H16MODE: fp16 level storage is on; each keypoint's octave picks the path.
+// The next work item of a wave from a counter in the workspace header: one
+// integer atomic per item, taken by whichever wave asks first.  Each item's
+// results go to slots fixed by its index, so they do not depend on which
+// wave computed them; waves whose items cost less take more of them.  Used
+// where items are long and uneven (descriptors: the window grows with the
+// keypoint's scale); for short items (orientation, with many rejected
+// candidates) the atomics on one address cost more than the balance gains.
+__device__ __forceinline__ int next_item(int* counter) {
+  int v = 0;
+  if ((threadIdx.x & 63) == 0) v = atomicAdd(counter, 1);
+  return __shfl(v, 0, 64);
+}
+
 template <bool H16MODE>
 __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, DevParams p) {
   // OC histogram columns per wave: lanes l, l + OC, ... share column l % OC
@@ -642,7 +656,10 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
   const ImgEntry* tab = hp.table;
   const LayoutCfg lc = layout_cfg(p);
   const int lane = threadIdx.x;
-  for (int g = blockIdx.x; g < total; g += gridDim.x) {
+  int* const queue = hp.queue;
+  int g_next = next_item(queue);
+  for (int g = g_next; g < total; g = g_next) {
+    g_next = next_item(queue);   // the wave's next keypoint, fetched while this one runs
     const int img = find_owner(kpp, n, g);
     const int q = g - kpp[img];
     const ImgEntry e = tab[img];

@@ -67,7 +67,8 @@ int main() {
     CHECK(hd.band_prefix >= hd.tile_prefix + (int64_t)kNumTileH * kMaxOct * (n + 1) * 4);
     CHECK(hd.cand_prefix >= hd.band_prefix + (n + 1) * 4);
     CHECK(hd.kp_prefix >= hd.cand_prefix + (n + 1) * 4);
-    CHECK(hd.bytes >= hd.kp_prefix + (n + 1) * 4 && hd.bytes % 256 == 0);
+    CHECK(hd.queue >= hd.kp_prefix + (n + 1) * 4);
+    CHECK(hd.bytes >= hd.queue + kQueues * 4 && hd.bytes % 256 == 0);
   }
   { int h = 0, w = 0; CHECK(sizeof(RefinedKp) == 48); CHECK(sizeof(ImgEntry) == 80); }
   printf("fails=%d\n", fails);
