@@ -62,6 +62,7 @@ struct LayoutCfg {
   int s;          // n_scales
   int border;
   int max_cand;
+  int max_kp;
   int h16;        // 1: octaves after the first hold fp16 levels
 };
 
@@ -102,6 +103,7 @@ struct RegionTail {
   int64_t n_ori;           // int32 [max_cand]
   int64_t angles;          // float [max_cand][kMaxPeaks]
   int64_t kp_off;          // int32 [max_cand]
+  int64_t kp_src;          // int32 [max_kp]: candidate * 32 + peak of each keypoint slot
   int64_t bytes;           // region size
 };
 
@@ -153,6 +155,8 @@ SIFT_HD void region_walk(int h, int w, const LayoutCfg& c, int want, OctView* v,
   off = align_up(off + (int64_t)c.max_cand * kMaxPeaks * 4, 256);
   t->kp_off = off;
   off = align_up(off + (int64_t)c.max_cand * 4, 256);
+  t->kp_src = off;
+  off = align_up(off + (int64_t)c.max_kp * 4, 256);
   t->bytes = off;
 }
 
@@ -262,6 +266,7 @@ SIFT_HD LayoutCfg layout_cfg(const DevParams& p) {
   c.s = p.s;
   c.border = p.border;
   c.max_cand = p.max_cand;
+  c.max_kp = p.max_kp;
   c.h16 = p.h16;
   return c;
 }

@@ -612,6 +612,8 @@ __global__ __launch_bounds__(256) void k_ori_scan(char* ws, HdrPtrs hp, int n, D
   const int nc = min(cnt[kCntCand], p.max_cand);
   const int* n_ori = reinterpret_cast<const int*>(ws + e.region + rt.n_ori);
   int* kp_off = reinterpret_cast<int*>(ws + e.region + rt.kp_off);
+  int* kp_src = reinterpret_cast<int*>(ws + e.region + rt.kp_src);
+  static_assert(kMaxPeaks <= 32, "peak index in five bits");
   int base = 0;
   for (int c0 = 0; c0 < nc; c0 += 256) {
     const int idx = c0 + threadIdx.x;
@@ -619,6 +621,11 @@ __global__ __launch_bounds__(256) void k_ori_scan(char* ws, HdrPtrs hp, int n, D
     int tot;
     const int ex = block_excl_scan256(v, s_wave, &tot);
     if (idx < nc) kp_off[idx] = base + ex;
+    // the inverse: which candidate and peak each keypoint slot describes
+    for (int r = 0; r < v && base + ex + r < p.max_kp; ++r) {
+      SIFT_CHECK_INDEX(base + ex + r, p.max_kp);
+      kp_src[base + ex + r] = idx * 32 + r;
+    }
     base += tot;
   }
   if (threadIdx.x == 0) {
@@ -665,16 +672,12 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
     const ImgEntry e = tab[img];
     const RegionTail rt = region_tail(e.h, e.w, lc);
     const int* cnt = counters_of(ws, e);
-    const int nc = min(cnt[kCntCand], p.max_cand);
-    const int* kp_off = reinterpret_cast<const int*>(ws + e.region + rt.kp_off);
-    // candidate j with kp_off[j] <= q < kp_off[j] + n_ori[j]
-    int lo = 0, hi = nc;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (kp_off[mid] <= q) lo = mid; else hi = mid;
-    }
-    const int j = lo;
-    const int pk_idx = q - kp_off[j];
+    // the candidate and peak this keypoint slot describes (written by the
+    // orientation scan)
+    SIFT_CHECK_INDEX(q, p.max_kp);
+    const int src = reinterpret_cast<const int*>(ws + e.region + rt.kp_src)[q];
+    const int j = src >> 5;
+    const int pk_idx = src & 31;
     const RefinedKp kp = reinterpret_cast<const RefinedKp*>(ws + e.region + rt.refined)[j];
     const int4 cd = reinterpret_cast<const int4*>(ws + e.region + rt.cands)[j];
     const float angle =

@@ -22,7 +22,7 @@ int main() {
     int minside = need << (n_oct - 1);
     if (up) minside = (minside + 1) / 2;
     int h = rnd(minside, minside + 900), w = rnd(minside, minside + 900);
-    LayoutCfg c{n_oct + up, up, s, border, rnd(1, 5000)};
+    LayoutCfg c{n_oct + up, up, s, border, rnd(1, 5000), rnd(1, 70000)};
     RegionTail t = region_tail(h, w, c);
     int64_t prev_end = 256;
     int bands = 0;
@@ -59,7 +59,8 @@ int main() {
     CHECK(t.n_ori >= t.refined + (int64_t)c.max_cand * 48);
     CHECK(t.angles >= t.n_ori + (int64_t)c.max_cand * 4);
     CHECK(t.kp_off >= t.angles + (int64_t)c.max_cand * kMaxPeaks * 4);
-    CHECK(t.bytes >= t.kp_off + (int64_t)c.max_cand * 4);
+    CHECK(t.kp_src >= t.kp_off + (int64_t)c.max_cand * 4);
+    CHECK(t.bytes >= t.kp_src + (int64_t)c.max_kp * 4);
   }
   for (int n = 1; n < 300; n += 37) {
     Header hd; make_header(n, &hd); int h = n, w = 0;
