@@ -242,10 +242,12 @@ __device__ __forceinline__ float load_lv(const gchar* row, uint32_t byte_off) {
   if (H16) return (float)*reinterpret_cast<const ghalf*>(row + byte_off);
   return *reinterpret_cast<const gfloat*>(row + byte_off);
 }
+// Level stores are marked non-temporal: a level is read back by a later
+// launch, after far more data than the caches hold has passed through them.
 template <bool H16>
 __device__ __forceinline__ void store_lv(gchar* row, uint32_t byte_off, float v) {
-  if (H16) *reinterpret_cast<ghalf*>(row + byte_off) = f16_rn(v);
-  else *reinterpret_cast<gfloat*>(row + byte_off) = v;
+  if (H16) __builtin_nontemporal_store(f16_rn(v), reinterpret_cast<ghalf*>(row + byte_off));
+  else __builtin_nontemporal_store(v, reinterpret_cast<gfloat*>(row + byte_off));
 }
 // Four consecutive elements at a byte offset aligned to their total size (16
 // bytes fp32, 8 bytes fp16): one wide store.
@@ -262,7 +264,7 @@ __device__ __forceinline__ void store4_lv(gchar* row, uint32_t byte_off, const f
     u32x2 q;
     q.x = lo;
     q.y = hi;
-    *reinterpret_cast<gu32x2*>(row + byte_off) = q;
+    __builtin_nontemporal_store(q, reinterpret_cast<gu32x2*>(row + byte_off));
   } else {
     typedef __attribute__((address_space(1))) f32x4 gf32x4;
     f32x4 q;
@@ -270,7 +272,7 @@ __device__ __forceinline__ void store4_lv(gchar* row, uint32_t byte_off, const f
     q.y = v[1];
     q.z = v[2];
     q.w = v[3];
-    *reinterpret_cast<gf32x4*>(row + byte_off) = q;
+    __builtin_nontemporal_store(q, reinterpret_cast<gf32x4*>(row + byte_off));
   }
 }
 
