@@ -437,6 +437,11 @@ __global__ __launch_bounds__(256) void k_refine(char* ws, HdrPtrs hp, int n, Dev
 // neighbours.
 
 // H16MODE: fp16 level storage is on; each keypoint's octave picks the path.
+// Batches of at most this many images keep their candidate (orientation) and
+// keypoint (descriptor) prefix tables in LDS.
+constexpr int kOriLdsPrefix = 1024;
+constexpr int kDescLdsPrefix = 319;
+
 // The next work item of a wave from a counter in the workspace header: one
 // integer atomic per item, taken by whichever wave asks first.  Each item's
 // results go to slots fixed by its index, so they do not depend on which
@@ -457,7 +462,15 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
   constexpr int OC = 16, OG = 64 / OC;
   __shared__ float s_hist[4][kOriBins * OC];
   __shared__ float s_bins[4][kOriBins];
+  // the candidate prefix over the images, in LDS when it fits: each
+  // candidate's image is then found without global-memory round trips
+  __shared__ int s_cp[kOriLdsPrefix + 1];
   const int* cp = hp.cand_prefix;
+  const bool cp_lds = n <= kOriLdsPrefix;
+  if (cp_lds) {
+    for (int i = threadIdx.x; i <= n; i += blockDim.x) s_cp[i] = cp[i];
+    __syncthreads();
+  }
   const int total = cp[n];
   const ImgEntry* tab = hp.table;
   const LayoutCfg lc = layout_cfg(p);
@@ -466,8 +479,8 @@ __global__ __launch_bounds__(256) void k_orient(char* ws, HdrPtrs hp, int n, Dev
   float* bins = s_bins[wave];
   const int nwaves = gridDim.x * 4;
   for (int g = blockIdx.x * 4 + wave; g < total; g += nwaves) {
-    const int img = find_owner(cp, n, g);
-    const int j = g - cp[img];
+    const int img = cp_lds ? find_owner(s_cp, n, g) : find_owner(cp, n, g);
+    const int j = g - (cp_lds ? s_cp[img] : cp[img]);
     const ImgEntry e = tab[img];
     const RegionTail rt = region_tail(e.h, e.w, lc);
     const RefinedKp kp = reinterpret_cast<const RefinedKp*>(ws + e.region + rt.refined)[j];
@@ -658,7 +671,15 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
   // (their unrolled size loop needs the registers a third resident wave would)
   constexpr int DC = ND == 1 ? 16 : 32, NG = 64 / DC;
   __shared__ float hist[kDescDim * DC];
+  // the keypoint prefix over the images, in LDS when it fits (kept small:
+  // the LDS of 16 resident waves per CU is nearly all histograms)
+  __shared__ int s_kpp[kDescLdsPrefix + 1];
   const int* kpp = hp.kp_prefix;
+  const bool kpp_lds = n <= kDescLdsPrefix;
+  if (kpp_lds) {
+    for (int i = threadIdx.x; i <= n; i += 64) s_kpp[i] = kpp[i];
+    wave_lds_sync();
+  }
   const int total = kpp[n];
   const ImgEntry* tab = hp.table;
   const LayoutCfg lc = layout_cfg(p);
@@ -667,8 +688,8 @@ __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n
   int g_next = next_item(queue);
   for (int g = g_next; g < total; g = g_next) {
     g_next = next_item(queue);   // the wave's next keypoint, fetched while this one runs
-    const int img = find_owner(kpp, n, g);
-    const int q = g - kpp[img];
+    const int img = kpp_lds ? find_owner(s_kpp, n, g) : find_owner(kpp, n, g);
+    const int q = g - (kpp_lds ? s_kpp[img] : kpp[img]);
     const ImgEntry e = tab[img];
     const RegionTail rt = region_tail(e.h, e.w, lc);
     const int* cnt = counters_of(ws, e);
