@@ -662,7 +662,9 @@ __global__ __launch_bounds__(256) void k_ori_scan(char* ws, HdrPtrs hp, int n, D
 // RootSIFT (L1 normalise, square root).
 
 // ND: the number of domain sizes the code is unrolled for (1, or the most).
-// The bound of 16 resident groups per CU caps registers at 128 per lane.
+// The launch bound asks for 16 resident groups per CU (128 registers per
+// lane): the one-size build fits; the pooled-size build takes about 180
+// registers and 8 groups are resident per CU.
 // H16MODE: fp16 level storage is on; each keypoint's octave picks the path.
 template <int ND, bool H16MODE>
 __global__ __launch_bounds__(64, 16) void k_describe(char* ws, HdrPtrs hp, int n, DevParams p) {
