@@ -8,7 +8,7 @@ bit.  Needs an MI355X."""
 import pytest
 
 from paper_2605_17869_amd import synth
-from gpu_util import digest, extract_batch, require_gpu, say
+from gpu_util import digest, extract, extract_batch, require_gpu, say
 
 pytestmark = pytest.mark.gpu
 
@@ -96,3 +96,30 @@ def test_matcher_and_verifier_in_bounds():
     n = bounds_violations(reset=True)
     say(f"matching and verification: {n} out-of-range accesses")
     assert n == 0
+
+
+def test_batch_beyond_the_lds_prefix_tables():
+    """One sub-batch of 1,030 small images: more than the orientation and
+    descriptor kernels keep of the batch's prefix tables in LDS, so both search
+    them in global memory.  Every image's results equal those of extracting it
+    alone, and the bounds-checked library finds nothing out of range."""
+    require_gpu()
+    from paper_2605_17869_amd import Extractor, bounds_violations
+    sizes = [(64 + (k % 5) * 8, 64 + (k % 7) * 8) for k in range(1030)]
+    imgs = [synth.blob_image(5000 + k, h, w, 6) for k, (h, w) in enumerate(sizes)]
+    settings = dict(synth.BASE_SETTINGS, n_octaves=2, max_keypoints=256, max_candidates=256,
+                    n_streams=1)
+    say(f"{len(imgs)} images in one launch sequence")
+    batch = [digest(r[0], r[1]) + str(r[2:]) for r in extract_batch(Extractor(settings), imgs)]
+    ex = Extractor(settings)
+    alone = []
+    for im in imgs[::103]:
+        kp, desc, nf, nc = extract(ex, im)
+        alone.append(digest(kp, desc) + str((nf, nc)))
+    assert alone == batch[::103]
+    bounds_violations(reset=True)
+    checked = [digest(r[0], r[1]) + str(r[2:])
+               for r in extract_batch(Extractor(settings, bounds_checked=True), imgs)]
+    n = bounds_violations(reset=True)
+    say(f"1,030 images: {n} out-of-range accesses")
+    assert n == 0 and checked == batch
